@@ -1,0 +1,109 @@
+"""Build and load the C part of the oracle (oracle.c) with gcc, via ctypes.
+
+Test infrastructure only: see the package docstring.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (plain C, gcc -O2)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
+            i32p = ctypes.POINTER(ctypes.c_int32)
+            u64p = ctypes.POINTER(ctypes.c_uint64)
+            lib.oracle_count_range.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p,
+                                               ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, u64p]
+            lib.oracle_count_range.restype = ctypes.c_int
+            lib.oracle_tm_torus.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int, u64p]
+            lib.oracle_tm_torus.restype = ctypes.c_int
+            _lib = lib
+        return _lib
+
+
+def default_threads() -> int:
+    """Host threads to use: the CPUs this process may run on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def count_range(n_spins: int, bond_i, bond_j, bond_J, first: int, count: int,
+                n_threads: int | None = None) -> np.ndarray:
+    """g over configurations with index in [first, first+count): uint64 [2S+1][N+1]."""
+    lib = _load()
+    bi, pbi = _i32(bond_i)
+    bj, pbj = _i32(bond_j)
+    bJ, pbJ = _i32(bond_J)
+    S = int(np.abs(bJ.astype(np.int64)).sum())
+    g = np.zeros((2 * S + 1, n_spins + 1), dtype=np.uint64)
+    rc = lib.oracle_count_range(int(n_spins), int(bi.shape[0]), pbi, pbj, pbJ,
+                                int(first), int(count), int(n_threads or default_threads()),
+                                g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    if rc != 0:
+        raise ValueError(f"oracle_count_range failed ({rc})")
+    return g
+
+
+def count_all(n_spins: int, bond_i, bond_j, bond_J, n_threads: int | None = None) -> np.ndarray:
+    """g(E, M) of all 2^N configurations (the definition, brute force)."""
+    return count_range(n_spins, bond_i, bond_j, bond_J, 0, 1 << n_spins, n_threads)
+
+
+def tm_torus(Jh, Jv, n_threads: int | None = None) -> np.ndarray:
+    """Exact g of a square torus from the transfer matrix: uint64 [2S+1][N+1].
+
+    Jh, Jv: int [Ly][Lx] coupling grids (see oracle.c for the bond geometry).
+    """
+    lib = _load()
+    Jh = np.asarray(Jh, dtype=np.int32)
+    Jv = np.asarray(Jv, dtype=np.int32)
+    if Jv.shape != Jh.shape:
+        raise ValueError("Jh and Jv must have the same shape")
+    if Jh.shape[1] > Jh.shape[0]:
+        # Transfer along the longer side: the transposed torus (rows <-> columns,
+        # horizontal <-> vertical bonds) is the same graph with sites renamed,
+        # so its g is identical and the row states are fewer.
+        Jh, Jv = Jv.T, Jh.T
+    Jh, pJh = _i32(Jh)
+    Jv, pJv = _i32(Jv)
+    Ly, Lx = Jh.shape
+    S = int(np.abs(Jh.astype(np.int64)).sum() + np.abs(Jv.astype(np.int64)).sum())
+    g = np.zeros((2 * S + 1, Lx * Ly + 1), dtype=np.uint64)
+    rc = lib.oracle_tm_torus(int(Lx), int(Ly), pJh, pJv, int(n_threads or default_threads()),
+                             g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    if rc != 0:
+        raise ValueError(f"oracle_tm_torus failed ({rc})")
+    return g

@@ -1,0 +1,227 @@
+/*
+ * CPU oracle for the exact Ising degeneracy table g(E, M).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library calls, links or loads
+ * this file; it exists so that the tests and the benchmark's CPU baseline can
+ * check the GPU path against an independent, obviously correct computation.
+ * It shares no code, header or table with the GPU path.
+ *
+ * Definitions followed (Peretyatko et al., Section 2):
+ *   - Eq. (1): H = -(1/2) sum_i sum_{j in nbr(i)} J_ij S_i S_j - h sum_i S_i.
+ *     The 1/2 over the double neighbour sum counts every bond once, so for a
+ *     bond multiset the exchange energy is E = -sum_b J_b s_i s_j.
+ *   - Every one of the 2^N configurations is assigned the pair (E, M), where
+ *     M is the spin excess sum_i s_i; g(E, M) is the number of configurations
+ *     with that pair (the degeneracy multiplicity discussed after Eq. (2)).
+ *   - Section 3a: the spin excess follows from the number of "up" bits.
+ *
+ * Conventions: configuration index c in [0, 2^N); bit u of c set means
+ * s_u = +1.  n_up = popcount(c), M = 2 n_up - N.  Output table g is dense,
+ * row-major [2S+1][N+1], row E + S, column n_up, S = sum_b |J_b|.
+ *
+ * Two independent exact counts live here:
+ *   oracle_count_range : the definition written out (loop over configurations,
+ *                        loop over bonds), for an index range of configurations;
+ *   oracle_tm_torus    : a row-to-row transfer-matrix count for square tori with
+ *                        per-bond couplings (a different algorithm, used to pin
+ *                        the brute force and to reach the 6x6 / 8x5 sizes).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+/* ---------------------------------------------------------------------- */
+/* Brute force: the definition, configuration by configuration.           */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  int n, nb;
+  const int32_t *bi, *bj, *bJ;
+  int64_t S;
+  uint64_t lo, hi;
+  uint64_t *table; /* private [2S+1][n+1] */
+} count_job;
+
+static void *count_worker(void *arg) {
+  count_job *jb = (count_job *)arg;
+  const int nm = jb->n + 1;
+  for (uint64_t c = jb->lo; c < jb->hi; ++c) {
+    int64_t e = 0;
+    for (int b = 0; b < jb->nb; ++b) {
+      const int64_t si = ((c >> jb->bi[b]) & 1u) ? 1 : -1;
+      const int64_t sj = ((c >> jb->bj[b]) & 1u) ? 1 : -1;
+      e -= (int64_t)jb->bJ[b] * si * sj;
+    }
+    int up = 0;
+    for (int u = 0; u < jb->n; ++u) up += (int)((c >> u) & 1u);
+    jb->table[(size_t)(e + jb->S) * nm + up] += 1;
+  }
+  return NULL;
+}
+
+/* Count configurations with index in [first, first + count) into g (added,
+ * not overwritten).  Returns 0 on success, <0 on bad arguments. */
+int oracle_count_range(int n, int nb, const int32_t *bi, const int32_t *bj,
+                       const int32_t *bJ, uint64_t first, uint64_t count,
+                       int n_threads, uint64_t *g) {
+  if (n < 1 || n > 62 || nb < 0 || n_threads < 1 || !g) return -1;
+  int64_t S = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (bi[b] < 0 || bi[b] >= n || bj[b] < 0 || bj[b] >= n) return -2;
+    S += bJ[b] < 0 ? -(int64_t)bJ[b] : bJ[b];
+  }
+  const uint64_t total = (uint64_t)1 << n;
+  if (first > total || count > total - first) return -3;
+  const size_t cells = (size_t)(2 * S + 1) * (size_t)(n + 1);
+  if (count == 0) return 0;
+  if ((uint64_t)n_threads > count) n_threads = (int)count;
+
+  count_job *jobs = (count_job *)calloc((size_t)n_threads, sizeof(count_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+  if (!jobs || !th) { free(jobs); free(th); return -4; }
+  const uint64_t per = count / (uint64_t)n_threads, rem = count % (uint64_t)n_threads;
+  uint64_t lo = first;
+  int rc = 0;
+  for (int t = 0; t < n_threads; ++t) {
+    const uint64_t len = per + ((uint64_t)t < rem ? 1 : 0);
+    jobs[t] = (count_job){n, nb, bi, bj, bJ, S, lo, lo + len,
+                          (uint64_t *)calloc(cells, sizeof(uint64_t))};
+    if (!jobs[t].table) { rc = -4; n_threads = t; break; }
+    lo += len;
+  }
+  if (rc == 0) {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, count_worker, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    for (int t = 0; t < n_threads; ++t)
+      for (size_t k = 0; k < cells; ++k) g[k] += jobs[t].table[k];
+  }
+  for (int t = 0; t < n_threads; ++t) free(jobs[t].table);
+  free(jobs); free(th);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Transfer matrix for an Lx x Ly square torus with per-bond couplings.     */
+/* ---------------------------------------------------------------------- */
+/* Site (x, y) is index y*Lx + x.  Jh[y*Lx + x] couples (x, y)-(x+1 mod Lx, y);
+ * Jv[y*Lx + x] couples (x, y)-(x, y+1 mod Ly).  A row state r has bit x set
+ * when s(x, y) = +1.  Fixing the first row a, F[r] is the (E, n_up) count of
+ * rows 0..y with row y in state r; adding a row adds its in-row bonds and the
+ * vertical bonds to the previous row; the last row closes onto row a. */
+
+static int64_t row_energy(int Lx, const int32_t *Jh_row, unsigned r) {
+  int64_t e = 0;
+  for (int x = 0; x < Lx; ++x) {
+    const int64_t s1 = ((r >> x) & 1u) ? 1 : -1;
+    const int64_t s2 = ((r >> ((x + 1) % Lx)) & 1u) ? 1 : -1;
+    e -= (int64_t)Jh_row[x] * s1 * s2;
+  }
+  return e;
+}
+
+static int64_t link_energy(int Lx, const int32_t *Jv_row, unsigned r_lo, unsigned r_hi) {
+  int64_t e = 0;
+  for (int x = 0; x < Lx; ++x) {
+    const int64_t s1 = ((r_lo >> x) & 1u) ? 1 : -1;
+    const int64_t s2 = ((r_hi >> x) & 1u) ? 1 : -1;
+    e -= (int64_t)Jv_row[x] * s1 * s2;
+  }
+  return e;
+}
+
+typedef struct {
+  int Lx, Ly;
+  const int32_t *Jh, *Jv;
+  int64_t S;
+  unsigned a_lo, a_hi;     /* first-row states handled by this worker */
+  uint64_t *table;         /* private [2S+1][N+1] */
+  int status;
+} tm_job;
+
+static void *tm_worker(void *arg) {
+  tm_job *jb = (tm_job *)arg;
+  const int Lx = jb->Lx, Ly = jb->Ly, N = Lx * Ly, nm = N + 1;
+  const unsigned R = 1u << Lx;
+  const int64_t ne = 2 * jb->S + 1;
+  const size_t poly = (size_t)ne * (size_t)nm;
+  uint64_t *F = (uint64_t *)malloc(sizeof(uint64_t) * poly * R);
+  uint64_t *G = (uint64_t *)malloc(sizeof(uint64_t) * poly * R);
+  int64_t *eintra = (int64_t *)malloc(sizeof(int64_t) * R * (size_t)Ly);
+  if (!F || !G || !eintra) { free(F); free(G); free(eintra); jb->status = -4; return NULL; }
+  for (int y = 0; y < Ly; ++y)
+    for (unsigned r = 0; r < R; ++r) eintra[(size_t)y * R + r] = row_energy(Lx, jb->Jh + y * Lx, r);
+
+  for (unsigned a = jb->a_lo; a < jb->a_hi; ++a) {
+    memset(F, 0, sizeof(uint64_t) * poly * R);
+    F[(size_t)a * poly + (size_t)(eintra[a] + jb->S) * nm + __builtin_popcount(a)] = 1;
+    for (int y = 1; y < Ly; ++y) {
+      memset(G, 0, sizeof(uint64_t) * poly * R);
+      for (unsigned r = 0; r < R; ++r) {
+        const uint64_t *src = F + (size_t)r * poly;
+        for (unsigned r2 = 0; r2 < R; ++r2) {
+          const int64_t de = eintra[(size_t)y * R + r2] + link_energy(Lx, jb->Jv + (y - 1) * Lx, r, r2);
+          const int dn = __builtin_popcount(r2);
+          uint64_t *dst = G + (size_t)r2 * poly;
+          for (int64_t e = 0; e < ne; ++e) {
+            const int64_t e2 = e + de;
+            if (e2 < 0 || e2 >= ne) continue;
+            const uint64_t *s = src + (size_t)e * nm;
+            uint64_t *d = dst + (size_t)e2 * nm;
+            for (int n = 0; n + dn < nm; ++n) d[n + dn] += s[n];
+          }
+        }
+      }
+      uint64_t *t = F; F = G; G = t;
+    }
+    for (unsigned r = 0; r < R; ++r) {
+      const int64_t de = link_energy(Lx, jb->Jv + (Ly - 1) * Lx, r, a);
+      const uint64_t *src = F + (size_t)r * poly;
+      for (int64_t e = 0; e < ne; ++e) {
+        const int64_t e2 = e + de;
+        if (e2 < 0 || e2 >= ne) continue;
+        for (int n = 0; n < nm; ++n) jb->table[(size_t)e2 * nm + n] += src[(size_t)e * nm + n];
+      }
+    }
+  }
+  free(F); free(G); free(eintra);
+  return NULL;
+}
+
+/* Exact g for the torus into g (overwritten), S = sum |Jh| + sum |Jv|. */
+int oracle_tm_torus(int Lx, int Ly, const int32_t *Jh, const int32_t *Jv,
+                    int n_threads, uint64_t *g) {
+  if (Lx < 2 || Ly < 2 || Lx > 16 || Lx * Ly > 62 || n_threads < 1 || !g) return -1;
+  int64_t S = 0;
+  for (int k = 0; k < Lx * Ly; ++k) {
+    S += Jh[k] < 0 ? -(int64_t)Jh[k] : Jh[k];
+    S += Jv[k] < 0 ? -(int64_t)Jv[k] : Jv[k];
+  }
+  const int N = Lx * Ly;
+  const size_t cells = (size_t)(2 * S + 1) * (size_t)(N + 1);
+  const unsigned R = 1u << Lx;
+  if ((unsigned)n_threads > R) n_threads = (int)R;
+  tm_job *jobs = (tm_job *)calloc((size_t)n_threads, sizeof(tm_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+  if (!jobs || !th) { free(jobs); free(th); return -4; }
+  int rc = 0, made = 0;
+  for (int t = 0; t < n_threads; ++t) {
+    const unsigned lo = (unsigned)((uint64_t)R * t / n_threads);
+    const unsigned hi = (unsigned)((uint64_t)R * (t + 1) / n_threads);
+    jobs[t] = (tm_job){Lx, Ly, Jh, Jv, S, lo, hi, (uint64_t *)calloc(cells, sizeof(uint64_t)), 0};
+    if (!jobs[t].table) { rc = -4; break; }
+    made = t + 1;
+  }
+  if (rc == 0) {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, tm_worker, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    memset(g, 0, cells * sizeof(uint64_t));
+    for (int t = 0; t < n_threads; ++t) {
+      if (jobs[t].status) rc = jobs[t].status;
+      for (size_t k = 0; k < cells; ++k) g[k] += jobs[t].table[k];
+    }
+  }
+  for (int t = 0; t < made; ++t) free(jobs[t].table);
+  free(jobs); free(th);
+  return rc;
+}

@@ -1,0 +1,234 @@
+"""Pins of the CPU oracle against facts outside itself (no GPU).
+
+Each test compares the oracle with something it does not compute itself:
+the paper's printed Table 1, closed forms, invariants the paper states, an
+independent algorithm (transfer matrix vs brute force), or a high-precision
+evaluation.  A planted-mistake section checks that the pins are sensitive.
+"""
+from math import comb
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from conftest import load_table1, nonzero_bins
+from oracle import bruteforce, closed_forms, native, thermo
+from paper_1110_2561_amd import lattice as L
+
+
+def _g(lat, **kw):
+    return native.count_all(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J, **kw)
+
+
+def _tm(lat):
+    return native.tm_torus(*L.torus_coupling_grids(lat))
+
+
+# --------------------------------------------------------------------------
+# g(E, M): the paper's Table 1 (Section 4)
+# --------------------------------------------------------------------------
+
+def test_table1_fixture_is_consistent():
+    t = load_table1()
+    assert len(t) == 80
+    assert sum(t.values()) == 1 << 16                      # 65536 configurations
+    for n_up in range(17):                                 # binomial marginal (Section 2)
+        assert sum(v for (e, m), v in t.items() if m == 2 * n_up - 16) == comb(16, n_up)
+
+
+def test_bruteforce_matches_table1():
+    lat = L.square_torus(4, 4)
+    g = _g(lat)
+    assert nonzero_bins(g, -lat.abs_coupling_sum, 16) == load_table1()
+
+
+def test_transfer_matrix_matches_table1():
+    lat = L.square_torus(4, 4)
+    assert nonzero_bins(_tm(lat), -32, 16) == load_table1()
+
+
+def test_energy_from_satisfied_bond_count():
+    # Section 3c: for the uniform torus E = 2(N - En), En the number of
+    # satisfied bonds.  Check per configuration on the 4x4 torus.
+    lat = L.square_torus(4, 4)
+    c = np.arange(1 << 16)
+    s = ((c[:, None] >> np.arange(16)) & 1) * 2 - 1
+    sat = (s[:, lat.bond_i] == s[:, lat.bond_j]).sum(axis=1)
+    E_def = -(s[:, lat.bond_i] * s[:, lat.bond_j]).sum(axis=1)
+    np.testing.assert_array_equal(E_def, 2 * (16 - sat))
+
+
+# --------------------------------------------------------------------------
+# g(E, M): invariants and independent implementations
+# --------------------------------------------------------------------------
+
+RANDOM_CASES = [
+    L.square_torus(3, 3, L.choice_couplings(18, 7)),
+    L.square_torus(3, 4, L.pm_couplings(24, 11)),
+    L.triangular_free(11, 4, L.choice_couplings(L.triangular_free(11, 4).n_bonds, 3)),
+    L.random_bond_lattice(9, 20, 5),           # multigraph with repeated pairs
+    L.random_bond_lattice(13, 30, 6, values=(-3, 1)),
+    L.ring(7, L.pm_couplings(7, 2)),
+]
+
+
+@pytest.mark.parametrize("lat", RANDOM_CASES, ids=lambda l: f"{l.kind}{l.n_spins}")
+def test_bruteforce_c_equals_numpy_definition(lat):
+    np.testing.assert_array_equal(_g(lat), bruteforce.g_numpy(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J))
+
+
+@pytest.mark.parametrize("lat", RANDOM_CASES, ids=lambda l: f"{l.kind}{l.n_spins}")
+def test_total_binomial_and_flip_symmetry(lat):
+    g = _g(lat)
+    N = lat.n_spins
+    assert int(g.sum()) == 1 << N
+    np.testing.assert_array_equal(g.sum(axis=0).astype(object), closed_forms.binomial_marginal(N))
+    # global spin flip leaves E unchanged and maps n_up -> N - n_up
+    np.testing.assert_array_equal(g, g[:, ::-1])
+
+
+def test_count_range_is_additive():
+    lat = L.square_torus(4, 5, L.pm_couplings(40, 4))
+    whole = _g(lat)
+    cuts = [0, 1, 777, 1 << 12, (1 << 20) - 5, 1 << 20]
+    parts = sum(native.count_range(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J, a, b - a)
+                for a, b in zip(cuts[:-1], cuts[1:]))
+    np.testing.assert_array_equal(parts, whole)
+
+
+@pytest.mark.parametrize("N", [3, 4, 5, 8, 11, 16])
+def test_ring_closed_form_degeneracies(N):
+    np.testing.assert_array_equal(_g(L.ring(N)), closed_forms.ring_g(N))
+
+
+@pytest.mark.parametrize("shape,seed", [((3, 3), 1), ((3, 4), 2), ((4, 3), 3), ((2, 5), 4),
+                                        ((5, 2), 5), ((4, 5), 6), ((2, 2), 7)])
+def test_transfer_matrix_equals_bruteforce_random_J(shape, seed):
+    lat = L.square_torus(*shape, L.choice_couplings(2 * shape[0] * shape[1], seed))
+    np.testing.assert_array_equal(_tm(lat), _g(lat))
+
+
+def test_uniform_ferromagnet_special_values_6x6():
+    g = _tm(L.square_torus(6, 6))
+    N, S = 36, 72
+    assert int(g.sum()) == 1 << 36
+    assert g[-S + S, 0] == 1 and g[-S + S, N] == 1          # two ground states
+    assert g[72 + S, 18] == 2                              # two checkerboards
+    assert g[-64 + S, 1] == 36 and g[-64 + S, 35] == 36    # single flips
+    assert int((g > 0).sum()) == 482
+
+
+def test_pm_8x5_transfer_matrix_invariants():
+    lat = L.workload("torus8x5_pm")["lattice"]
+    g = _tm(lat)
+    assert int(g.sum()) == 1 << 40
+    np.testing.assert_array_equal(g, g[:, ::-1])
+    np.testing.assert_array_equal(g.sum(axis=0).astype(object), closed_forms.binomial_marginal(40))
+    assert int(g.max()) > 1 << 32                          # needs 64-bit bins
+
+
+# --------------------------------------------------------------------------
+# log Z and moments (Eq. (2))
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n", [(2, 2), (3, 3), (3, 4), (4, 3), (4, 4), (3, 5), (4, 5), (6, 6)])
+def test_logz_matches_kaufman(m, n):
+    g = _tm(L.square_torus(n, m))       # Lx = n sites per row, m rows
+    T = np.array([0.5, 1.0, 2.0, 2.269, 3.0, 5.0])
+    lz = thermo.log_z(g, -2 * m * n, m * n, T, [0.0])[:, 0]
+    ref = np.array([float(closed_forms.kaufman_logz(m, n, t)) for t in T])
+    np.testing.assert_allclose(lz, ref, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("N", [3, 5, 8, 16])
+def test_logz_matches_ring_with_field(N):
+    g = _g(L.ring(N))
+    T = np.array([0.5, 1.0, 3.0])
+    h = np.array([-1.0, 0.0, 0.1, 0.5, 2.0])
+    lz = thermo.log_z(g, -N, N, T, h)
+    ref = np.array([[float(closed_forms.ring_logz(N, t, hh)) for hh in h] for t in T])
+    np.testing.assert_allclose(lz, ref, rtol=1e-13, atol=1e-14)
+
+
+def test_logz_fp64_within_1e12_of_50_digit_sum():
+    lat = L.square_torus(4, 5, L.choice_couplings(40, 9))
+    g = _tm(lat)
+    S = lat.abs_coupling_sum
+    for T, h in [(0.5, 0.0), (0.5, 2.0), (2.269, 0.1), (5.0, -1.0)]:
+        lz = thermo.log_z(g, -S, 20, [T], [h])[0, 0]
+        ref = float(thermo.log_z_mp(g, -S, 20, T, h))
+        assert abs(lz - ref) <= 1e-12 * abs(ref)
+
+
+def test_moments_match_derivatives_of_ring_closed_form():
+    N = 8
+    g = _g(L.ring(N))
+    for T, h in [(0.7, 0.0), (1.0, 0.3), (2.5, -0.8)]:
+        mE, mM, C, chi = (a[0, 0] for a in thermo.moments(g, -N, N, [T], [h]))
+        with mp.workdps(40):
+            f = lambda t, hh: closed_forms.ring_logz(N, t, hh)
+            dT = mp.diff(lambda t: f(t, h), T)
+            dh = mp.diff(lambda hh: f(T, hh), h)
+            dhh = mp.diff(lambda hh: f(T, hh), h, 2)
+            # <E - hM> = T^2 dlogZ/dT ; <M> = T dlogZ/dh ; Var(M) = T^2 d2logZ/dh2
+            U = lambda t: t * t * mp.diff(lambda tt: f(tt, h), t)
+            dU = mp.diff(U, T)
+        assert mM == pytest.approx(float(T * dh), rel=1e-12, abs=1e-12)
+        assert mE - h * mM == pytest.approx(float(T * T * dT), rel=1e-12)
+        assert chi == pytest.approx(float(T * dhh), rel=1e-11)
+        assert C == pytest.approx(float(dU), rel=1e-11)     # C = d<H>/dT
+
+
+def test_moments_match_derivatives_of_kaufman():
+    m, n = 4, 4
+    g = _tm(L.square_torus(n, m))
+    for T in [1.0, 2.269, 4.0]:
+        mE, mM, C, chi = (a[0, 0] for a in thermo.moments(g, -32, 16, [T], [0.0]))
+        with mp.workdps(40):
+            f = lambda t: closed_forms.kaufman_logz(m, n, t)
+            U = lambda t: t * t * mp.diff(f, t)
+            e_ref = U(T)
+            c_ref = mp.diff(U, T)
+        assert mE == pytest.approx(float(e_ref), rel=1e-12)
+        assert C == pytest.approx(float(c_ref), rel=1e-11)
+        assert abs(mM) < 1e-13      # <M> = 0 at h = 0, up to rounding
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes: each plausible slip in what the oracle is fed or how it
+# counts must break at least one pin above.
+# --------------------------------------------------------------------------
+
+def test_planted_dropped_bond_breaks_table1():
+    lat = L.square_torus(4, 4)
+    keep = np.arange(lat.n_bonds) != 5
+    g = native.count_all(16, lat.bond_i[keep], lat.bond_j[keep], lat.bond_J[keep])
+    assert nonzero_bins(g, -31, 16) != load_table1()
+
+
+def test_planted_sign_flip_breaks_table1():
+    lat = L.square_torus(4, 4)
+    g = native.count_all(16, lat.bond_i, lat.bond_j, -lat.bond_J)
+    assert nonzero_bins(g, -32, 16) != load_table1()
+
+
+def test_planted_transposed_couplings_break_tm_parity():
+    lat = L.square_torus(3, 4, L.choice_couplings(24, 2))
+    Jh, Jv = L.torus_coupling_grids(lat)
+    assert not np.array_equal(native.tm_torus(Jv, Jh), _g(lat))
+
+
+def test_planted_wrong_magnetisation_index_breaks_ring_pin():
+    # M taken as 2 n_up instead of 2 n_up - N (a dropped offset) must fail the
+    # 1D closed form once h != 0, while the correct index passes it.
+    g = _g(L.ring(5))
+    ref = float(closed_forms.ring_logz(5, 1.0, 0.5))
+    assert abs(thermo.log_z(g, -5, 5, [1.0], [0.5])[0, 0] - ref) < 1e-13
+    assert abs(thermo.log_z(g, -5, 0, [1.0], [0.5])[0, 0] - ref) > 1e-3
+
+
+def test_planted_energy_offset_breaks_kaufman_pin():
+    g = _tm(L.square_torus(4, 4))
+    ref = float(closed_forms.kaufman_logz(4, 4, 2.0))
+    assert abs(thermo.log_z(g, -32, 16, [2.0], [0.0])[0, 0] - ref) < 1e-13
+    assert abs(thermo.log_z(g, -31, 16, [2.0], [0.0])[0, 0] - ref) > 1e-3
