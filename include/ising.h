@@ -1,0 +1,154 @@
+/*
+ * ising.h — C ABI of libising: exact degeneracy tables g(E, M) and partition
+ * functions of finite Ising systems, computed on an AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The operation (Peretyatko et al., "Rigorous Calculation of the Partition
+ * Function for the Finite Number of Ising Spins"):
+ *   - Section 2, Eq. (1): H = -(1/2) sum_i sum_{j in nbr(i)} J_ij S_i S_j - h sum_i S_i.
+ *     The factor 1/2 over the double neighbour sum counts each bond once, so
+ *     for a bond multiset the exchange energy is E = -sum_b J_b s_i s_j and
+ *     H = E - h M, with M = sum_i s_i the spin excess.
+ *   - Section 2, the discussion after Eq. (2): every one of the 2^N
+ *     configurations maps to a pair (E, M); the degeneracy multiplicity
+ *     g(E, M) is the number of configurations with that pair.
+ *   - Section 2, Eq. (2): Z_N(h, T) = sum over configurations of exp(-H/T)
+ *     = sum_{E,M} g(E, M) exp(-(E - h M)/T), with k_B = 1.
+ *   - Section 3 (a-d): the configurations are enumerated exhaustively as
+ *     bit vectors and the work is split into independent ranges.
+ *
+ * Conventions used throughout:
+ *   - spin u is "up" (s_u = +1) when its bit is set; n_up = number of up
+ *     spins; M = 2 n_up - N.
+ *   - the dense table g is uint64, row-major [n_e][n_m] with n_e = 2S + 1,
+ *     n_m = N + 1, S = sum_b |J_b| over the bonds as given; entry
+ *     g[(E - e_min) * n_m + n_up] with e_min = -S.
+ *   - all functions are extern "C", never throw, and return ising_status
+ *     (0 = success).  On failure ising_last_error() gives a message for the
+ *     calling thread.
+ *   - device pointers are addresses in the current HIP device's memory
+ *     (e.g. torch.Tensor.data_ptr() of a CUDA tensor on ROCm); `stream` is a
+ *     hipStream_t passed as void* (NULL = the default stream).  Calls that
+ *     take a stream are asynchronous and stream-ordered: launch errors are
+ *     returned at once, faults surface at the caller's next synchronisation.
+ *   - the caller owns every buffer passed in; the library never frees or
+ *     reallocates caller memory.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ising_status {
+  ISING_OK = 0,
+  ISING_EINVAL = -1,            /* bad argument (null pointer, bad size, bad shape) */
+  ISING_ETOO_MANY_SPINS = -2,   /* n_spins < 1 or > 64 */
+  ISING_EBOND = -3,             /* bond endpoint out of range, or a self-bond i == j */
+  ISING_ERANGE = -4,            /* couplings too large: S > 2^20, or histogram exceeds LDS */
+  ISING_EHIP = -5,              /* a HIP runtime call failed (message has the HIP error) */
+  ISING_ENOMEM = -6,            /* host or device allocation failed */
+  ISING_EUNSUPPORTED = -7       /* valid input outside what this build handles
+                                   (e.g. more than 8 distinct coupling values) */
+} ising_status;
+
+/* A finite Ising system: N spins and a multiset of bonds (i, j, J) with
+ * integer couplings (Section 2, Eq. (1): the paper's J_ij may be sign-changing
+ * and long-range).  Repeated pairs are allowed and add up.  All three arrays
+ * are host pointers of length n_bonds; they are read during
+ * ising_plan_create only and may be freed afterwards. */
+typedef struct ising_lattice {
+  int32_t n_spins;              /* 1 .. 64 */
+  int32_t n_bonds;              /* >= 0 */
+  const int32_t *bond_i;        /* endpoint sites, 0 .. n_spins-1 */
+  const int32_t *bond_j;        /* endpoint sites, != bond_i */
+  const int32_t *bond_J;        /* couplings, |J| <= 2^20 */
+} ising_lattice;
+
+/* Optional launch/decomposition choices; 0 in a field means "choose". */
+typedef struct ising_tune {
+  int32_t inner_bits;           /* k: configurations per chunk = 2^k (tile_bits .. 25) */
+  int32_t tile_bits;            /* j: independent-set spins walked per block of 2^j steps (1 .. 6) */
+  int32_t waves_per_block;      /* 1 .. 16 (64 lanes per wave) */
+  int32_t replicas;             /* LDS histogram copies per block: 1, 2, 4, 8 or 16 */
+  int32_t max_blocks;           /* grid cap */
+} ising_tune;
+
+/* Opaque, immutable after creation.  Safe to use from several threads and
+ * streams at once with distinct outputs.  Device constants are uploaded on
+ * the first launch on each device and owned by the plan. */
+typedef struct ising_plan ising_plan;
+
+/* Validate the lattice, merge repeated pairs, choose the spin ordering, the
+ * chunk decomposition and the histogram geometry.  Host-only: makes no HIP
+ * call.  `tune` may be NULL.  On success *plan receives a new plan that the
+ * caller releases with ising_plan_destroy. */
+ising_status ising_plan_create(const ising_lattice *lattice, const ising_tune *tune,
+                               ising_plan **plan);
+
+/* Release a plan and its device constants.  NULL is accepted.  The caller
+ * must ensure no launch that uses the plan is still running. */
+ising_status ising_plan_destroy(ising_plan *plan);
+
+/* Dense table shape of the plan: *n_e = 2S + 1, *n_m = N + 1, *e_min = -S. */
+ising_status ising_hist_shape(const ising_plan *plan, int32_t *n_e, int32_t *n_m,
+                              int32_t *e_min);
+
+/* Enumeration order (Section 3d: the configuration space is split into
+ * independent ranges).  The plan renames spins to bit positions: site u is
+ * bit bit_of_site[u] (array of n_spins entries, filled if non-NULL).  Chunk c
+ * is the set of 2^inner_bits configurations whose bits inner_bits .. N-1 equal
+ * c; there are *n_chunks = 2^(N - inner_bits) chunks.  Any of the outputs may
+ * be NULL. */
+ising_status ising_plan_layout(const ising_plan *plan, int32_t *bit_of_site,
+                               int32_t *inner_bits, int32_t *tile_bits, uint64_t *n_chunks);
+
+/* g(E, M) of all 2^N configurations into the device table g_dev
+ * ([n_e][n_m] uint64, overwritten). */
+ising_status ising_enumerate(const ising_plan *plan, uint64_t *g_dev, void *stream);
+
+/* Add to g_dev the counts of the configurations in chunks
+ * [first_chunk, first_chunk + n_chunks) (see ising_plan_layout).  Disjoint
+ * ranges sum to the full table, which is how work is sharded or resumed.
+ * Fails with ISING_EINVAL if the range exceeds the chunk count. */
+ising_status ising_enumerate_range(const ising_plan *plan, uint64_t first_chunk,
+                                   uint64_t n_chunks, uint64_t *g_dev, void *stream);
+
+/* log Z(T, h) of Eq. (2) in FP64 from a dense table on the device:
+ *   logz[a * nh + b] = log sum_{g>0} g(E,M) exp(-(E - h_b M)/T_a).
+ * g_dev: [n_e][n_m] uint64 with n_m = n_spins + 1 and e_min its first energy.
+ * T_dev[nT], h_dev[nh], logz_dev[nT * nh]: FP64 device arrays.  T must be
+ * positive and finite; other T give NaN.  An all-zero table gives -inf. */
+ising_status ising_logz(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min,
+                        int32_t n_spins, const double *T_dev, int32_t nT,
+                        const double *h_dev, int32_t nh, double *logz_dev, void *stream);
+
+/* Thermal moments under p(E, M) = g exp(-(E - hM)/T) / Z, each [nT][nh] FP64:
+ *   mean_E = <E> (exchange energy), mean_M = <M>,
+ *   heat_capacity = Var(E - h M) / T^2, susceptibility = Var(M) / T
+ * (totals, not per spin; variances from centred sums).  Any output may be
+ * NULL; logz_dev (optional) receives log Z as in ising_logz. */
+ising_status ising_moments(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min,
+                           int32_t n_spins, const double *T_dev, int32_t nT,
+                           const double *h_dev, int32_t nh, double *logz_dev,
+                           double *mean_E, double *mean_M, double *heat_capacity,
+                           double *susceptibility, void *stream);
+
+/* Static text for a status code. */
+const char *ising_status_str(ising_status status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *ising_last_error(void);
+
+/* Library version string. */
+const char *ising_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

@@ -1,0 +1,70 @@
+// Library-internal definitions shared by the host plan code and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/ising.h"
+
+namespace ising {
+
+constexpr int kMaxSpins = 64;
+constexpr int kMaxClasses = 8;      // distinct nonzero merged couplings
+constexpr int kMaxTile = 6;         // tile bits j (independent-set spins)
+constexpr int kMaxInner = 25;       // inner bits k (configurations per chunk 2^k)
+constexpr int kMaxMiddle = kMaxInner - 1;
+constexpr int kLdsBytes = 160 * 1024;
+constexpr int kWave = 64;
+constexpr int kMaxDevices = 64;
+
+// Constants one enumeration launch reads (uploaded once per device).
+// Spin indices are plan bit positions: bits [0, tile) are the tile (an
+// independent set), [tile, inner) the middle bits, [inner, n) the chunk
+// prefix.
+struct DevPlan {
+  int32_t n;             // spins
+  int32_t inner;         // k
+  int32_t tile;          // j
+  int32_t n_classes;     // distinct merged couplings
+  int32_t estep;         // every E lies on e_base + estep * Z
+  int32_t e_base;        // lowest compact energy (>= -S_eff)
+  int32_t n_ec;          // compact energy rows
+  int32_t W;             // compact row stride (bins per energy row) = n + 1
+  int32_t R;             // LDS replicas (power of two)
+  int32_t e_min;         // dense table: e_min = -S
+  int32_t n_m;           // dense table columns = n + 1
+  int32_t pad0;
+  int32_t class_J[kMaxClasses];
+  int32_t hdeg[kMaxSpins];                  // sum_c J_c * deg_c(i)
+  int32_t kmid[kMaxMiddle][kMaxTile];       // byte change of tile delta i when middle bit m goes up
+  uint64_t mask[kMaxSpins][kMaxClasses];    // neighbours of bit i with coupling class c
+};
+
+}  // namespace ising
+
+struct ising_plan {
+  // input as given
+  int32_t n_spins = 0;
+  int32_t n_bonds = 0;
+  int64_t S = 0;                 // sum |J_b| over the input bonds
+  // ordering and decomposition
+  int32_t bit_of_site[ising::kMaxSpins] = {};
+  int32_t site_of_bit[ising::kMaxSpins] = {};
+  uint64_t n_chunks = 0;
+  int32_t waves_per_block = 16;
+  int32_t max_blocks = 0;
+  int32_t blocks_per_cu = 1;
+  int64_t n_merged_pairs = 0;
+  ising::DevPlan dev{};
+  // per-device constant copies (lazy)
+  std::mutex mu;
+  void *dev_copy[ising::kMaxDevices] = {};
+};
+
+namespace ising {
+void set_error(const std::string &msg);
+ising_status fail(ising_status st, const std::string &msg);
+const void *plan_device_constants(ising_plan *plan, int device, ising_status *st);
+}  // namespace ising

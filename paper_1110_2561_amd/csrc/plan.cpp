@@ -1,0 +1,246 @@
+// Host-side plan construction for libising: validation, coupling merge,
+// spin ordering, chunk decomposition and histogram geometry.  No HIP calls:
+// this file builds with any C++17 compiler (the library builds it with hipcc).
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ising {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ising_status fail(ising_status st, const std::string &msg) {
+  g_last_error = std::string(ising_status_str(st)) + ": " + msg;
+  return st;
+}
+
+static int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+}  // namespace ising
+
+using namespace ising;
+
+extern "C" const char *ising_status_str(ising_status st) {
+  switch (st) {
+    case ISING_OK: return "ISING_OK";
+    case ISING_EINVAL: return "ISING_EINVAL";
+    case ISING_ETOO_MANY_SPINS: return "ISING_ETOO_MANY_SPINS";
+    case ISING_EBOND: return "ISING_EBOND";
+    case ISING_ERANGE: return "ISING_ERANGE";
+    case ISING_EHIP: return "ISING_EHIP";
+    case ISING_ENOMEM: return "ISING_ENOMEM";
+    case ISING_EUNSUPPORTED: return "ISING_EUNSUPPORTED";
+  }
+  return "ISING_UNKNOWN";
+}
+
+extern "C" const char *ising_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *ising_version(void) { return "libising 0.1 (gfx950)"; }
+
+extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_tune *tune,
+                                          ising_plan **out) {
+  if (!out) return fail(ISING_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (!lat) return fail(ISING_EINVAL, "lattice is NULL");
+  const int n = lat->n_spins;
+  if (n < 1 || n > kMaxSpins)
+    return fail(ISING_ETOO_MANY_SPINS, "n_spins = " + std::to_string(n) + " (must be 1..64)");
+  if (lat->n_bonds < 0) return fail(ISING_EINVAL, "n_bonds < 0");
+  if (lat->n_bonds > 0 && (!lat->bond_i || !lat->bond_j || !lat->bond_J))
+    return fail(ISING_EINVAL, "bond arrays are NULL");
+  ising_tune tn{};
+  if (tune) tn = *tune;
+  if (tn.inner_bits < 0 || tn.inner_bits > kMaxInner || tn.tile_bits < 0 || tn.tile_bits > kMaxTile ||
+      tn.waves_per_block < 0 || tn.waves_per_block > 16 || tn.max_blocks < 0 ||
+      (tn.replicas != 0 && (tn.replicas > 16 || (tn.replicas & (tn.replicas - 1)))))
+    return fail(ISING_EINVAL, "tune values out of range");
+
+  // ---- validate bonds and merge repeated pairs (E is linear in J per pair) ----
+  const int64_t kJmax = int64_t(1) << 20;
+  int64_t S = 0;
+  std::vector<int64_t> J(size_t(n) * n, 0);
+  for (int b = 0; b < lat->n_bonds; ++b) {
+    const int i = lat->bond_i[b], j = lat->bond_j[b];
+    const int64_t v = lat->bond_J[b];
+    if (i < 0 || i >= n || j < 0 || j >= n)
+      return fail(ISING_EBOND, "bond " + std::to_string(b) + " has an endpoint outside 0..n_spins-1");
+    if (i == j) return fail(ISING_EBOND, "bond " + std::to_string(b) + " is a self-bond");
+    if (v > kJmax || v < -kJmax) return fail(ISING_ERANGE, "|J| > 2^20 in bond " + std::to_string(b));
+    S += v < 0 ? -v : v;
+    if (S > kJmax) return fail(ISING_ERANGE, "sum |J| exceeds 2^20");
+    J[size_t(std::min(i, j)) * n + std::max(i, j)] += v;
+    J[size_t(std::max(i, j)) * n + std::min(i, j)] += v;
+  }
+
+  // ---- coupling classes and the compact energy lattice ----
+  std::vector<int64_t> classes;
+  int64_t S_eff = 0, E_ref = 0, n_pairs = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const int64_t v = J[size_t(i) * n + j];
+      if (!v) continue;
+      ++n_pairs;
+      S_eff += v < 0 ? -v : v;
+      E_ref -= v;  // all spins up: every pair contributes -J
+      if (std::find(classes.begin(), classes.end(), v) == classes.end()) classes.push_back(v);
+    }
+  if ((int)classes.size() > kMaxClasses)
+    return fail(ISING_EUNSUPPORTED, std::to_string(classes.size()) +
+                                        " distinct merged couplings (at most 8 supported)");
+  std::sort(classes.begin(), classes.end());
+  // Flipping spin i changes E by -2 s_new h_i, h_i = sum_j J_ij s_j, and
+  // h_i = sum_j J_ij (mod 2 g_i) with g_i = gcd_j |J_ij|; so every energy lies
+  // on E_ref + estep Z with estep = gcd_i gcd(2 |sum_j J_ij|, 4 g_i).
+  int64_t estep = 0;
+  std::vector<int> degree(n, 0);
+  for (int i = 0; i < n; ++i) {
+    int64_t gi = 0, sum = 0;
+    for (int j = 0; j < n; ++j) {
+      const int64_t v = J[size_t(i) * n + j];
+      if (!v) continue;
+      ++degree[i];
+      gi = std::gcd(gi, v < 0 ? -v : v);
+      sum += v;
+    }
+    if (!gi) continue;
+    estep = std::gcd(estep, std::gcd(2 * (sum < 0 ? -sum : sum), 4 * gi));
+  }
+  if (!estep) estep = 1;
+  const int64_t e_base = E_ref - estep * floor_div(E_ref + S_eff, estep);
+  const int64_t n_ec = (S_eff - e_base) / estep + 1;
+  const int W = n + 1;
+
+  // ---- histogram replicas that fit the LDS ----
+  int R = tn.replicas ? tn.replicas : 16;
+  while (R > 1 && n_ec * W * R * 4 > kLdsBytes) R >>= 1;
+  if (n_ec * W * R * 4 > kLdsBytes)
+    return fail(ISING_ERANGE, "compact histogram of " + std::to_string(n_ec) + " x " + std::to_string(W) +
+                                  " bins exceeds the 160 KB LDS");
+  const int wpb = tn.waves_per_block ? tn.waves_per_block : 16;
+  // The enumeration kernel reserves the whole 160 KB LDS of a CU (a static
+  // array, so histogram addresses need no base add): one block per CU.
+  const int bpc = 1;
+
+  // ---- tile: a greedy independent set (no merged coupling between members) ----
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degree[a] > degree[b]; });
+  std::vector<int> tile;
+  const int tile_want = tn.tile_bits ? tn.tile_bits : kMaxTile;
+  for (int s : order) {
+    if ((int)tile.size() >= tile_want) break;
+    bool ok = true;
+    for (int t : tile)
+      if (J[size_t(s) * n + t]) { ok = false; break; }
+    if (ok) tile.push_back(s);
+  }
+  const int TJ = std::max(1, std::min<int>((int)tile.size(), n));
+  if (tn.tile_bits && TJ != tn.tile_bits)
+    return fail(ISING_EINVAL, "no independent set of " + std::to_string(tn.tile_bits) + " spins");
+
+  // ---- inner bits k: enough chunks for several tasks per block ----
+  int k;
+  if (tn.inner_bits) {
+    k = tn.inner_bits;
+    if (k < TJ || k > n) return fail(ISING_EINVAL, "inner_bits must lie in [tile_bits, n_spins]");
+  } else {
+    const int lanes_log2 = 8 /* 256 CUs */ + (bpc > 1 ? 1 : 0) + 6 + (31 - __builtin_clz(unsigned(wpb)));
+    k = n - (lanes_log2 + 2);
+    k = std::max(TJ, std::min(std::min(k, n), kMaxInner));
+  }
+  // every u32 LDS counter must stay below 2^32 between flushes:
+  // one task adds at most (lanes sharing a replica) * 2^k to a counter.
+  const uint64_t lanes_per_replica = uint64_t(kWave) * wpb / R;
+  if (lanes_per_replica << k >= (uint64_t(1) << 32)) {
+    if (tn.inner_bits) return fail(ISING_EINVAL, "inner_bits too large for the counter width");
+    while (k > TJ && (lanes_per_replica << k) >= (uint64_t(1) << 32)) --k;
+    if ((lanes_per_replica << k) >= (uint64_t(1) << 32))
+      return fail(ISING_EUNSUPPORTED, "no chunk size keeps LDS counters below 2^32");
+  }
+
+  // ---- bit order: tile, then middle, then prefix ----
+  ising_plan *p = new (std::nothrow) ising_plan();
+  if (!p) return fail(ISING_ENOMEM, "plan allocation");
+  std::vector<char> used(n, 0);
+  int bit = 0;
+  for (int t = 0; t < TJ; ++t) { p->site_of_bit[bit++] = tile[t]; used[tile[t]] = 1; }
+  for (int s : order)
+    if (!used[s]) { p->site_of_bit[bit++] = s; used[s] = 1; }
+  for (int b = 0; b < n; ++b) p->bit_of_site[p->site_of_bit[b]] = b;
+
+  p->n_spins = n;
+  p->n_bonds = lat->n_bonds;
+  p->S = S;
+  p->n_chunks = uint64_t(1) << (n - k);
+  p->waves_per_block = wpb;
+  p->max_blocks = tn.max_blocks;
+  p->blocks_per_cu = bpc;
+  p->n_merged_pairs = n_pairs;
+
+  DevPlan &d = p->dev;
+  d.n = n;
+  d.inner = k;
+  d.tile = TJ;
+  d.n_classes = (int)classes.size();
+  d.estep = (int32_t)estep;
+  d.e_base = (int32_t)e_base;
+  d.n_ec = (int32_t)n_ec;
+  d.W = W;
+  d.R = R;
+  d.e_min = (int32_t)-S;
+  d.n_m = n + 1;
+  for (int c = 0; c < d.n_classes; ++c) d.class_J[c] = (int32_t)classes[c];
+  for (int b = 0; b < n; ++b) {
+    const int s = p->site_of_bit[b];
+    int64_t hd = 0;
+    for (int b2 = 0; b2 < n; ++b2) {
+      const int64_t v = J[size_t(s) * n + p->site_of_bit[b2]];
+      if (!v) continue;
+      const int c = int(std::find(classes.begin(), classes.end(), v) - classes.begin());
+      d.mask[b][c] |= uint64_t(1) << b2;
+      hd += v;
+    }
+    d.hdeg[b] = (int32_t)hd;
+  }
+  const int64_t row_bytes = int64_t(W) * R * 4;
+  for (int m = TJ; m < k; ++m)
+    for (int i = 0; i < TJ; ++i) {
+      const int64_t v = J[size_t(p->site_of_bit[m]) * n + p->site_of_bit[i]];
+      // tile spin i's up-flip delta, in bytes, changes by this when bit m goes up
+      d.kmid[m - TJ][i] = (int32_t)((-4 * v / estep) * row_bytes);
+    }
+  *out = p;
+  set_error("");
+  return ISING_OK;
+}
+
+extern "C" ising_status ising_hist_shape(const ising_plan *p, int32_t *n_e, int32_t *n_m, int32_t *e_min) {
+  if (!p) return fail(ISING_EINVAL, "plan is NULL");
+  if (n_e) *n_e = (int32_t)(2 * p->S + 1);
+  if (n_m) *n_m = p->n_spins + 1;
+  if (e_min) *e_min = (int32_t)-p->S;
+  return ISING_OK;
+}
+
+extern "C" ising_status ising_plan_layout(const ising_plan *p, int32_t *bit_of_site, int32_t *inner_bits,
+                                          int32_t *tile_bits, uint64_t *n_chunks) {
+  if (!p) return fail(ISING_EINVAL, "plan is NULL");
+  if (bit_of_site) std::memcpy(bit_of_site, p->bit_of_site, sizeof(int32_t) * p->n_spins);
+  if (inner_bits) *inner_bits = p->dev.inner;
+  if (tile_bits) *tile_bits = p->dev.tile;
+  if (n_chunks) *n_chunks = p->n_chunks;
+  return ISING_OK;
+}

@@ -1,0 +1,179 @@
+// FP64 evaluation of the partition function (Peretyatko et al., Section 2,
+// Eq. (2)) and its moments from a dense degeneracy table on the device.
+//
+// Grouping the configurations of Eq. (2) by (E, M):
+//   Z(T, h) = sum_{E,M} g(E, M) exp(-(E - h M)/T),  H = E - h M (Eq. (1)).
+// One block per (T, h) point:
+//   pass 1  m = max over nonzero bins of a = ln g - (E - h M)/T;
+//   pass 2  Z' = sum exp(a - m), and the weighted sums of E and M;
+//   pass 3  centred sums of (H - <H>)^2 and (M - <M>)^2;
+//   log Z = m + ln Z', <E>, <M>, C = Var(H)/T^2, chi = Var(M)/T.
+// Reductions run in a fixed order (wave shuffles, then waves), so results are
+// reproducible run to run.  The table is small (<= ~10^5 bins) and read from
+// L2 by every block; this kernel is negligible next to the enumeration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+
+namespace ising {
+
+constexpr int kThermoThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block-wide sums of up to 3 values; every thread gets the totals.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
+  __syncthreads();
+  if (lane == 0) { sh[wv] = a; sh[8 + wv] = b; sh[16 + wv] = c; }
+  __syncthreads();
+  a = b = c = 0.0;
+  for (int w = 0; w < nw; ++w) { a += sh[w]; b += sh[8 + w]; c += sh[16 + w]; }
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  v = -INFINITY;
+  for (int w = 0; w < nw; ++w) v = fmax(v, sh[w]);
+  return v;
+}
+
+__global__ __launch_bounds__(kThermoThreads) void k_thermo(
+    const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
+    const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
+    double *__restrict__ logz, double *__restrict__ mean_E, double *__restrict__ mean_M,
+    double *__restrict__ heat, double *__restrict__ susc) {
+  __shared__ double sh[24];
+  const int pt = blockIdx.x;
+  const int ia = pt / nh, ib = pt - ia * nh;
+  const double T = Tg[ia], h = hg[ib];
+  const int bins = n_e * n_m;
+  const bool want_moments = mean_E || mean_M || heat || susc;
+  if (!(T > 0.0) || !isfinite(T) || !isfinite(h)) {
+    if (threadIdx.x == 0) {
+      if (logz) logz[pt] = NAN;
+      if (mean_E) mean_E[pt] = NAN;
+      if (mean_M) mean_M[pt] = NAN;
+      if (heat) heat[pt] = NAN;
+      if (susc) susc[pt] = NAN;
+    }
+    return;
+  }
+  const double inv_T = 1.0 / T;
+
+  // pass 1: the largest exponent
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+    const unsigned long long v = g[i];
+    if (!v) continue;
+    const int e = i / n_m, nu = i - e * n_m;
+    const double E = double(e + e_min), M = double(2 * nu - n_spins);
+    m = fmax(m, log(double(v)) - (E - h * M) * inv_T);
+  }
+  m = block_max(m, sh);
+  if (m == -INFINITY) {
+    if (threadIdx.x == 0) {
+      if (logz) logz[pt] = -INFINITY;
+      if (mean_E) mean_E[pt] = NAN;
+      if (mean_M) mean_M[pt] = NAN;
+      if (heat) heat[pt] = NAN;
+      if (susc) susc[pt] = NAN;
+    }
+    return;
+  }
+
+  // pass 2: Z' and first moments
+  double z = 0.0, se = 0.0, sm = 0.0;
+  for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+    const unsigned long long v = g[i];
+    if (!v) continue;
+    const int e = i / n_m, nu = i - e * n_m;
+    const double E = double(e + e_min), M = double(2 * nu - n_spins);
+    const double w = exp(log(double(v)) - (E - h * M) * inv_T - m);
+    z += w;
+    se += w * E;
+    sm += w * M;
+  }
+  block_sum3(z, se, sm, sh);
+  const double mE = se / z, mM = sm / z;
+  if (threadIdx.x == 0 && logz) logz[pt] = m + log(z);
+  if (!want_moments) return;
+
+  // pass 3: centred second moments of H = E - hM and of M
+  const double mH = mE - h * mM;
+  double vh = 0.0, vm = 0.0, unused = 0.0;
+  for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+    const unsigned long long v = g[i];
+    if (!v) continue;
+    const int e = i / n_m, nu = i - e * n_m;
+    const double E = double(e + e_min), M = double(2 * nu - n_spins);
+    const double w = exp(log(double(v)) - (E - h * M) * inv_T - m);
+    const double dH = (E - h * M) - mH, dM = M - mM;
+    vh += w * dH * dH;
+    vm += w * dM * dM;
+  }
+  block_sum3(vh, vm, unused, sh);
+  if (threadIdx.x == 0) {
+    if (mean_E) mean_E[pt] = mE;
+    if (mean_M) mean_M[pt] = mM;
+    if (heat) heat[pt] = vh / z * inv_T * inv_T;
+    if (susc) susc[pt] = vm / z * inv_T;
+  }
+}
+
+static ising_status thermo_launch(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min, int32_t n_spins,
+                                  const double *T_dev, int32_t nT, const double *h_dev, int32_t nh, double *logz,
+                                  double *mE, double *mM, double *C, double *chi, void *stream) {
+  if (!g_dev) return fail(ISING_EINVAL, "g_dev is NULL");
+  if (n_spins < 1 || n_spins > kMaxSpins) return fail(ISING_ETOO_MANY_SPINS, "n_spins must be 1..64");
+  if (n_m != n_spins + 1) return fail(ISING_EINVAL, "n_m must equal n_spins + 1");
+  if (n_e < 1 || int64_t(n_e) * n_m > (int64_t(1) << 30)) return fail(ISING_EINVAL, "bad n_e");
+  if (nT < 0 || nh < 0) return fail(ISING_EINVAL, "negative grid size");
+  if (int64_t(nT) * nh > (int64_t(1) << 30)) return fail(ISING_EINVAL, "grid too large");
+  if (nT == 0 || nh == 0) return ISING_OK;
+  if (!T_dev || !h_dev) return fail(ISING_EINVAL, "T_dev or h_dev is NULL");
+  hipLaunchKernelGGL(k_thermo, dim3(unsigned(nT * nh)), dim3(kThermoThreads), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<const unsigned long long *>(g_dev), n_e, n_m, e_min, n_spins, T_dev, nT,
+                     h_dev, nh, logz, mE, mM, C, chi);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_thermo launch: ") + hipGetErrorString(e));
+  return ISING_OK;
+}
+
+}  // namespace ising
+
+using namespace ising;
+
+extern "C" ising_status ising_logz(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min, int32_t n_spins,
+                                   const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
+                                   double *logz_dev, void *stream) {
+  if (!logz_dev && nT > 0 && nh > 0) return fail(ISING_EINVAL, "logz_dev is NULL");
+  return thermo_launch(g_dev, n_e, n_m, e_min, n_spins, T_dev, nT, h_dev, nh, logz_dev, nullptr, nullptr,
+                       nullptr, nullptr, stream);
+}
+
+extern "C" ising_status ising_moments(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min,
+                                      int32_t n_spins, const double *T_dev, int32_t nT, const double *h_dev,
+                                      int32_t nh, double *logz_dev, double *mean_E, double *mean_M,
+                                      double *heat_capacity, double *susceptibility, void *stream) {
+  return thermo_launch(g_dev, n_e, n_m, e_min, n_spins, T_dev, nT, h_dev, nh, logz_dev, mean_E, mean_M,
+                       heat_capacity, susceptibility, stream);
+}
