@@ -55,7 +55,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="torus6x6", choices=["torus6x6", "torus8x5_pm", "torus4x4"])
-    ap.add_argument("--cpu-sample-log2", type=int, default=28)
+    ap.add_argument("--cpu-sample-log2", type=int, default=31)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 

@@ -72,7 +72,7 @@ typedef struct ising_lattice {
 /* Optional launch/decomposition choices; 0 in a field means "choose". */
 typedef struct ising_tune {
   int32_t inner_bits;           /* k: configurations per chunk = 2^k (tile_bits .. 25) */
-  int32_t tile_bits;            /* j: independent-set spins walked per block of 2^j steps (1 .. 6) */
+  int32_t tile_bits;            /* j: independent-set spins walked per block of 2^j steps (1 .. 8) */
   int32_t waves_per_block;      /* 1 .. 16 (64 lanes per wave) */
   int32_t replicas;             /* LDS histogram copies per block: 1, 2, 4, 8 or 16 */
   int32_t max_blocks;           /* grid cap */

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libising.so")
+# ISING_LIBRARY may name another build of the same library (e.g. a debug build).
+LIB_PATH = os.environ.get("ISING_LIBRARY") or os.path.join(_HERE, "libising.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1110_2561_amd.build` "

@@ -23,8 +23,9 @@
 //     popcount of the spin word against its neighbour masks, and the D_i of
 //     tile spins coupled to it move by a plan constant.
 //   * Every configuration adds 1 to its (E, n_up) bin in an LDS histogram
-//     with R copies per block; lane l writes copy l mod R, so the 16 lanes
-//     an LDS atomic cycle serves hit distinct banks.  Counters are u32; the
+//     with R copies per block; lane l writes copy l mod R.  Copy-major words
+//     (bin * R + copy) and a bin-row stride that is a multiple of 4 keep the
+//     32 lanes one LDS cycle serves in distinct banks.  Counters are u32; the
 //     block flushes them (sum over copies, 64-bit global atomics into the
 //     dense uint64 table) before any can reach 2^32, and at exit.
 //   * No HBM traffic beyond the final flush: the kernel is bound by the LDS
@@ -46,14 +47,6 @@ namespace ising {
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
-
-// Local field h_b = sum_j J_bj s_j of plan bit b in the spin word x
-// (bit set = spin +1): 2 * sum_c J_c popcount(x & mask_bc) - sum_c J_c deg_bc.
-__device__ __forceinline__ int32_t local_field(const DevPlan *__restrict__ P, int b, uint64_t x, int nc) {
-  int32_t acc = 0;
-  for (int c = 0; c < nc; ++c) acc += P->class_J[c] * __popcll(x & P->mask[b][c]);
-  return 2 * acc - P->hdeg[b];
-}
 
 __device__ __forceinline__ void lds_count(char *hist, uint32_t byte_addr) {
   __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(hist + byte_addr), 1u, __ATOMIC_RELAXED,
@@ -77,29 +70,89 @@ __device__ __forceinline__ void tile_walk(uint32_t &A, const int32_t (&D)[TJ], c
   }
 }
 
+// Plan constants held in registers for the whole launch.  Per-site data sit
+// one site per lane (site b in lane b, N <= 64) and are fetched with
+// v_readlane at a wave-uniform index, so neither the chunk set-up nor the
+// walk issues a scalar memory load (whose wait would also drain the wave's
+// outstanding LDS atomics).
+template <int TJ, int NC>
+struct SiteTable {
+  uint32_t mlo[NC], mhi[NC];   // neighbour masks of the lane's site, per coupling class
+  int32_t hdeg;                // sum_c J_c deg_c of the lane's site
+  int32_t base;                // up_base of the lane's site
+  int32_t kmid[TJ];            // lane m: tile-delta changes when middle bit TJ + m flips up
+  int32_t jc[NC], step[NC];    // class couplings and byte steps (uniform)
+  int32_t n, k, e_base, estep, row_bytes, col_bytes;   // uniform
+
+  __device__ void load(const DevPlan *__restrict__ P, int lane) {
+    n = P->n;
+    k = P->inner;
+    e_base = P->e_base;
+    estep = P->estep;
+    row_bytes = P->W * P->R * 4;
+    col_bytes = P->R * 4;
+    const bool site = lane < n;
+    const int b = site ? lane : 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint64_t m = site ? P->mask[b][c] : 0ull;
+      mlo[c] = uint32_t(m);
+      mhi[c] = uint32_t(m >> 32);
+      jc[c] = P->class_J[c];
+      step[c] = P->cls_step[c];
+    }
+    hdeg = site ? P->hdeg[b] : 0;
+    base = site ? P->up_base[b] : 0;
+    const bool mid = lane < k - TJ;
+#pragma unroll
+    for (int i = 0; i < TJ; ++i) kmid[i] = mid ? P->kmid[mid ? lane : 0][i] : 0;
+  }
+
+  // popcount(x & mask of site b, class c) for a wave-uniform b
+  __device__ __forceinline__ int32_t pop(int b, int c, uint32_t xlo, uint32_t xhi) const {
+    return __popc(xlo & uint32_t(__builtin_amdgcn_readlane(int(mlo[c]), b))) +
+           __popc(xhi & uint32_t(__builtin_amdgcn_readlane(int(mhi[c]), b)));
+  }
+
+  // local field h_b = sum_j J_bj s_j
+  __device__ __forceinline__ int32_t field(int b, uint32_t xlo, uint32_t xhi) const {
+    int32_t acc = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc += jc[c] * pop(b, c, xlo, xhi);
+    return 2 * acc - __builtin_amdgcn_readlane(hdeg, b);
+  }
+
+  // histogram byte-offset change when bit b flips up
+  __device__ __forceinline__ int32_t up_delta(int b, uint32_t xlo, uint32_t xhi) const {
+    int32_t acc = __builtin_amdgcn_readlane(base, b);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc -= step[c] * pop(b, c, xlo, xhi);
+    return acc;
+  }
+};
+
 // All 2^k configurations of one chunk (prefix bits fixed).
-template <int TJ>
-__device__ void walk_chunk(const DevPlan *__restrict__ P, uint64_t chunk, uint32_t rep, char *hist) {
-  const int n = P->n, k = P->inner, nc = P->n_classes;
-  const int32_t estep = P->estep;
-  const int32_t row_bytes = P->W * P->R * 4;   // one compact energy row
-  const int32_t col_bytes = P->R * 4;          // one n_up column
+template <int TJ, int NC>
+__device__ void walk_chunk(const SiteTable<TJ, NC> &st, uint64_t chunk, uint32_t rep, char *hist) {
+  const int k = st.k;
   const uint64_t x0 = chunk << k;
+  const uint32_t x0lo = uint32_t(x0), x0hi = uint32_t(x0 >> 32);
 
   // Full (E, n_up) of the first configuration: E = -(1/2) sum_i s_i h_i.
   int32_t hs = 0;
-  for (int i = 0; i < n; ++i) {
-    const int32_t h = local_field(P, i, x0, nc);
+  for (int i = 0; i < st.n; ++i) {
+    const int32_t h = st.field(i, x0lo, x0hi);
     hs += ((x0 >> i) & 1) ? h : -h;
   }
   const int32_t E0 = -(hs / 2);
   const int32_t nup = __popcll(x0);
-  uint32_t A = uint32_t(((E0 - P->e_base) / estep) * row_bytes + nup * col_bytes) + rep * 4u;
+  uint32_t A = uint32_t(((E0 - st.e_base) / st.estep) * st.row_bytes + nup * st.col_bytes) + rep * 4u;
 
-  // Up-flip address change of each tile spin: dE = -2 h_i, dn_up = +1.
+  // Up-flip address change of each tile spin (its neighbours are all outside
+  // the tile, so these stay fixed while only tile bits flip).
   int32_t D[TJ];
 #pragma unroll
-  for (int i = 0; i < TJ; ++i) D[i] = (-2 * local_field(P, i, x0, nc) / estep) * row_bytes + col_bytes;
+  for (int i = 0; i < TJ; ++i) D[i] = st.up_delta(i, x0lo, x0hi);
 
   const uint32_t nblk = 1u << (k - TJ);
   for (uint32_t q = 0; q < nblk; ++q) {
@@ -113,14 +166,12 @@ __device__ void walk_chunk(const DevPlan *__restrict__ P, uint64_t chunk, uint32
       const int mm = __builtin_ctz(q1);
       const bool up = (((q1 ^ (q1 >> 1)) >> mm) & 1u) != 0;
       // current inner bits: tile at its end state, middle bits = gray(q)
-      const uint64_t tile_end = (q & 1) ? 0ull : (1ull << (TJ - 1));
-      const uint64_t xc = x0 | tile_end | (uint64_t(q ^ (q >> 1)) << TJ);
-      const int32_t hm = local_field(P, TJ + mm, xc, nc);
-      const int32_t dm = (-2 * hm / estep) * row_bytes + col_bytes;
+      const uint64_t inner = ((q & 1) ? 0ull : (1ull << (TJ - 1))) | (uint64_t(q ^ (q >> 1)) << TJ);
+      const int32_t dm = st.up_delta(TJ + mm, x0lo | uint32_t(inner), x0hi | uint32_t(inner >> 32));
       A = up ? A + uint32_t(dm) : A - uint32_t(dm);
 #pragma unroll
       for (int i = 0; i < TJ; ++i) {
-        const int32_t kv = P->kmid[mm][i];
+        const int32_t kv = __builtin_amdgcn_readlane(st.kmid[i], mm);
         D[i] = up ? D[i] + kv : D[i] - kv;
       }
     }
@@ -137,18 +188,22 @@ __device__ void flush_hist(const DevPlan *__restrict__ P, uint32_t *h, unsigned 
       s += h[b * R + r];
       h[b * R + r] = 0;
     }
-    if (s) {
-      const int e_idx = b / W, nu = b - e_idx * W;
+    const int e_idx = b / W, nu = b - e_idx * W;
+    if (s && nu < P->n_m) {
       const int E = P->e_base + e_idx * P->estep;
       atomicAdd(&g[size_t(E - P->e_min) * P->n_m + nu], s);
     }
   }
 }
 
-// Chunk c = (task_lo + t) * blockDim.x + threadIdx.x for task t of this block;
-// lanes outside [chunk_lo, chunk_hi) idle.  All threads of a block run the
+// Task t of this block covers chunks (task_lo + t) * blockDim.x + [0, blockDim.x),
+// one per thread; lanes whose chunk lies outside [chunk_lo, chunk_hi) idle.
+// Lanes l and l + 16 of a half-wave share LDS copy l mod 16; their chunks
+// differ in one prefix spin, so their n_up differ by one, and with a row
+// stride W = 0 (mod 4) their words fall in different banks (bank = 16 * (bin
+// mod 4) + copy on the 64-bank LDS).  All threads of a block run the
 // same number of tasks, so the barriers around periodic flushes are uniform.
-template <int TJ>
+template <int TJ, int NC>
 __global__ __launch_bounds__(1024) void k_enumerate(const DevPlan *__restrict__ P, uint64_t chunk_lo,
                                                     uint64_t chunk_hi, uint64_t task_lo, uint64_t n_tasks,
                                                     uint32_t flush_every, unsigned long long *__restrict__ g) {
@@ -159,11 +214,14 @@ __global__ __launch_bounds__(1024) void k_enumerate(const DevPlan *__restrict__ 
   const int words = P->n_ec * P->W * P->R;
   for (int w = threadIdx.x; w < words; w += blockDim.x) h32[w] = 0;
   __syncthreads();
-  const uint32_t rep = threadIdx.x & uint32_t(P->R - 1);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t rep = lane & uint32_t(P->R - 1);
+  SiteTable<TJ, NC> st;
+  st.load(P, int(lane));
   uint32_t since = 0;
   for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
     const uint64_t chunk = (task_lo + t) * blockDim.x + threadIdx.x;
-    if (chunk >= chunk_lo && chunk < chunk_hi) walk_chunk<TJ>(P, chunk, rep, hist);
+    if (chunk >= chunk_lo && chunk < chunk_hi) walk_chunk<TJ, NC>(st, chunk, rep, hist);
     if (++since == flush_every) {
       __syncthreads();
       flush_hist(P, h32, g);
@@ -209,12 +267,12 @@ const void *plan_device_constants(ising_plan *p, int device, ising_status *st) {
   return p->dev_copy[device];
 }
 
-template <int TJ>
+template <int TJ, int NC>
 static ising_status launch_tj(const DevPlan *dP, uint64_t lo, uint64_t hi, uint64_t task_lo, uint64_t n_tasks,
                               int grid, int block, uint32_t flush_every, size_t smem,
                               unsigned long long *g, hipStream_t s) {
   (void)smem;
-  hipLaunchKernelGGL(k_enumerate<TJ>, dim3(grid), dim3(block), 0, s, dP, lo, hi, task_lo, n_tasks,
+  hipLaunchKernelGGL((k_enumerate<TJ, NC>), dim3(grid), dim3(block), 0, s, dP, lo, hi, task_lo, n_tasks,
                      flush_every, g);
   HIP_TRY(hipGetLastError());
   return ISING_OK;
@@ -246,15 +304,26 @@ static ising_status enumerate_chunks(const ising_plan *pc, uint64_t first, uint6
   if (fe > 0x7FFFFFFFull) fe = 0x7FFFFFFFull;
   const size_t smem = size_t(d.n_ec) * d.W * d.R * 4;
   unsigned long long *g = reinterpret_cast<unsigned long long *>(g_dev);
+#define ISING_NC(TJ)                                                                                  \
+  switch (d.n_classes) {                                                                              \
+    case 1: return launch_tj<TJ, 1>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream); \
+    case 2: return launch_tj<TJ, 2>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream); \
+    case 4: return launch_tj<TJ, 4>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream); \
+    case 8: return launch_tj<TJ, 8>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream); \
+  }                                                                                                   \
+  break;
   switch (d.tile) {
-    case 1: return launch_tj<1>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream);
-    case 2: return launch_tj<2>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream);
-    case 3: return launch_tj<3>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream);
-    case 4: return launch_tj<4>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream);
-    case 5: return launch_tj<5>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream);
-    case 6: return launch_tj<6>(dP, lo, hi, task_lo, n_tasks, int(grid), block, uint32_t(fe), smem, g, stream);
+    case 1: ISING_NC(1)
+    case 2: ISING_NC(2)
+    case 3: ISING_NC(3)
+    case 4: ISING_NC(4)
+    case 5: ISING_NC(5)
+    case 6: ISING_NC(6)
+    case 7: ISING_NC(7)
+    case 8: ISING_NC(8)
   }
-  return fail(ISING_EUNSUPPORTED, "tile bits out of range");
+#undef ISING_NC
+  return fail(ISING_EUNSUPPORTED, "tile bits or class count out of range");
 }
 
 }  // namespace ising

@@ -12,7 +12,7 @@ namespace ising {
 
 constexpr int kMaxSpins = 64;
 constexpr int kMaxClasses = 8;      // distinct nonzero merged couplings
-constexpr int kMaxTile = 6;         // tile bits j (independent-set spins)
+constexpr int kMaxTile = 8;         // tile bits j (independent-set spins)
 constexpr int kMaxInner = 25;       // inner bits k (configurations per chunk 2^k)
 constexpr int kMaxMiddle = kMaxInner - 1;
 constexpr int kLdsBytes = 160 * 1024;
@@ -27,17 +27,22 @@ struct DevPlan {
   int32_t n;             // spins
   int32_t inner;         // k
   int32_t tile;          // j
-  int32_t n_classes;     // distinct merged couplings
+  int32_t n_classes;     // distinct merged couplings, padded to 1, 2, 4 or 8
   int32_t estep;         // every E lies on e_base + estep * Z
   int32_t e_base;        // lowest compact energy (>= -S_eff)
   int32_t n_ec;          // compact energy rows
-  int32_t W;             // compact row stride (bins per energy row) = n + 1
+  int32_t W;             // compact row stride: n + 1 rounded up to a multiple of 4
   int32_t R;             // LDS replicas (power of two)
   int32_t e_min;         // dense table: e_min = -S
   int32_t n_m;           // dense table columns = n + 1
   int32_t pad0;
   int32_t class_J[kMaxClasses];
-  int32_t hdeg[kMaxSpins];                  // sum_c J_c * deg_c(i)
+  // Histogram byte offset change when bit b flips up, in the state x:
+  //   up_base[b] - sum_c cls_step[c] * popcount(x & mask[b][c]),
+  // i.e. (-2 h_b / estep) * row + col with h_b = 2 sum_c J_c popc - hdeg[b].
+  int32_t cls_step[kMaxClasses];            // (4 J_c / estep) * row bytes
+  int32_t up_base[kMaxSpins];               // (2 hdeg[b] / estep) * row bytes + column bytes
+  int32_t hdeg[kMaxSpins];                  // sum_c J_c * deg_c(b)
   int32_t kmid[kMaxMiddle][kMaxTile];       // byte change of tile delta i when middle bit m goes up
   uint64_t mask[kMaxSpins][kMaxClasses];    // neighbours of bit i with coupling class c
 };

@@ -121,7 +121,9 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   if (!estep) estep = 1;
   const int64_t e_base = E_ref - estep * floor_div(E_ref + S_eff, estep);
   const int64_t n_ec = (S_eff - e_base) / estep + 1;
-  const int W = n + 1;
+  // Row stride: n + 1 columns rounded up to a multiple of 4, so that a bin's
+  // LDS bank group (bin mod 4) follows n_up mod 4 (see enumerate.hip).
+  const int W = (n + 1 + 3) & ~3;
 
   // ---- histogram replicas that fit the LDS ----
   int R = tn.replicas ? tn.replicas : 16;
@@ -157,8 +159,11 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
     k = tn.inner_bits;
     if (k < TJ || k > n) return fail(ISING_EINVAL, "inner_bits must lie in [tile_bits, n_spins]");
   } else {
+    // ~16 tasks per block on 256 CUs: chunk costs vary (ordered prefixes
+    // collide more in the LDS), and many short tasks per block even out
+    // the finishing times of the blocks.
     const int lanes_log2 = 8 /* 256 CUs */ + (bpc > 1 ? 1 : 0) + 6 + (31 - __builtin_clz(unsigned(wpb)));
-    k = n - (lanes_log2 + 2);
+    k = n - (lanes_log2 + 4);
     k = std::max(TJ, std::min(std::min(k, n), kMaxInner));
   }
   // every u32 LDS counter must stay below 2^32 between flushes:
@@ -194,7 +199,8 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   d.n = n;
   d.inner = k;
   d.tile = TJ;
-  d.n_classes = (int)classes.size();
+  d.n_classes = 1;
+  while (d.n_classes < (int)classes.size()) d.n_classes *= 2;   // kernels exist for 1, 2, 4, 8
   d.estep = (int32_t)estep;
   d.e_base = (int32_t)e_base;
   d.n_ec = (int32_t)n_ec;
@@ -202,7 +208,11 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   d.R = R;
   d.e_min = (int32_t)-S;
   d.n_m = n + 1;
-  for (int c = 0; c < d.n_classes; ++c) d.class_J[c] = (int32_t)classes[c];
+  const int64_t row_bytes = int64_t(W) * R * 4, col_bytes = int64_t(R) * 4;
+  for (int c = 0; c < (int)classes.size(); ++c) {
+    d.class_J[c] = (int32_t)classes[c];
+    d.cls_step[c] = (int32_t)((4 * classes[c] / estep) * row_bytes);   // estep divides 4 J_c
+  }
   for (int b = 0; b < n; ++b) {
     const int s = p->site_of_bit[b];
     int64_t hd = 0;
@@ -214,8 +224,8 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
       hd += v;
     }
     d.hdeg[b] = (int32_t)hd;
+    d.up_base[b] = (int32_t)((2 * hd / estep) * row_bytes + col_bytes);  // estep divides 2 hdeg
   }
-  const int64_t row_bytes = int64_t(W) * R * 4;
   for (int m = TJ; m < k; ++m)
     for (int i = 0; i < TJ; ++i) {
       const int64_t v = J[size_t(p->site_of_bit[m]) * n + p->site_of_bit[i]];

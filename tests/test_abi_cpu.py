@@ -65,7 +65,7 @@ def test_plan_create_rejects_bad_input(lib, n, bi, bj, bJ, code):
 
 def test_plan_create_rejects_bad_tune(lib):
     lat = L.square_torus(3, 3)
-    for tune in (lib.ising_tune(0, 7, 0, 0, 0), lib.ising_tune(0, 0, 17, 0, 0), lib.ising_tune(0, 0, 0, 3, 0),
+    for tune in (lib.ising_tune(0, 9, 0, 0, 0), lib.ising_tune(0, 0, 17, 0, 0), lib.ising_tune(0, 0, 0, 3, 0),
                  lib.ising_tune(26, 0, 0, 0, 0), lib.ising_tune(2, 4, 0, 0, 0)):
         rc, _ = _create(lib, lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J, tune)
         assert rc == -1
