@@ -30,6 +30,35 @@ LDS_ATOMIC_PEAK = 256 * 16 * 2.4e9
 # Integer VALU: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (non-packed 32-bit ops).
 INT_VALU_PEAK = 256 * 64 * 2.4e9
 
+# Hardware-counter figures of k_enumerate on the 6x6 workload, from the
+# rocprofv3 runs summarised in profiles/ (k_enumerate_torus6x6_*.txt).  They
+# hold only for the kernel sources they were taken on: if the sources' hash
+# differs, the figures are reported as null.
+COUNTERS = {
+    "sources": ["paper_1110_2561_amd/csrc/enumerate.hip", "paper_1110_2561_amd/csrc/plan.cpp",
+                "paper_1110_2561_amd/csrc/internal.h"],
+    "sha256": "8382edbec6341ebe8163d8be8cb3c23846226af73bb425cb77bdb436a112b666",
+    "workload": "torus6x6",
+    # FETCH_SIZE 64.5 KiB x 2.0 + WRITE_SIZE 896.1 KiB x 1.0 per launch; the
+    # factors are what a 512 MiB copy kernel reads on the same counters.
+    "hbm_bytes_per_launch": int((64.5 * 2.0 + 896.09375 * 1.0) * 1024),
+    # SQ_INSTS_VALU_INT32 x 64 lanes / 2^36 configurations
+    "int32_valu_per_config": 1145449772 * 64 / 2 ** 36,
+    # SQ_INSTS_VALU x 64 lanes / 2^36 configurations (all VALU)
+    "valu_per_config": 1236714060 * 64 / 2 ** 36,
+}
+
+
+def counters_valid(workload: str) -> bool:
+    import hashlib
+    if workload != COUNTERS["workload"]:
+        return False
+    h = hashlib.sha256()
+    for f in COUNTERS["sources"]:
+        with open(os.path.join(_ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest() == COUNTERS["sha256"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -49,6 +78,21 @@ def cpu_baseline(lat, sample_log2: int) -> dict:
                       f"brute force over bonds, {dt:.1f} s wall"}
 
 
+def copy_calibration(nbytes: int) -> int:
+    """A plain copy kernel of known size: it reads and writes nbytes once per
+    launch, which calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = nbytes // 8
+    src = torch.arange(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copied {n * 8} bytes x 3")
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,7 +101,13 @@ def main() -> int:
     ap.add_argument("--workload", default="torus6x6", choices=["torus6x6", "torus8x5_pm", "torus4x4"])
     ap.add_argument("--cpu-sample-log2", type=int, default=31)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-bits", type=int, default=0, help="plan tile width (0 = the plan's choice)")
+    ap.add_argument("--inner-bits", type=int, default=0, help="plan chunk width (0 = the plan's choice)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -75,7 +125,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     w = L.workload(args.workload)
     lat, T, h = w["lattice"], w["T"], w["h"]
-    plan = api.Plan(lat)
+    tuned = bool(args.tile_bits or args.inner_bits)
+    plan = api.Plan(lat, api.Tune(inner_bits=args.inner_bits, tile_bits=args.tile_bits) if tuned else None)
     configs = 1 << lat.n_spins
     g = plan.new_table()
     Tt = torch.as_tensor(T, dtype=torch.float64, device="cuda")
@@ -112,6 +163,7 @@ def main() -> int:
     log(f"enumerate launch {kern_ms:.3f} ms avg, step {ms_per_step:.3f} ms, "
         f"log Z finite: {bool(torch.isfinite(out['log_z']).all())}")
 
+    valid = counters_valid(args.workload) and not tuned
     line = {
         "metric": METRIC,
         "value": value,
@@ -142,9 +194,18 @@ def main() -> int:
             "peak": LDS_ATOMIC_PEAK / 1e12,
             "unit": "Tops/s",
             "frac": achieved / LDS_ATOMIC_PEAK,
-            "traffic": None,
+            "traffic": COUNTERS["hbm_bytes_per_launch"] if valid else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "k_enumerate (event-timed with its zero-fill)",
             "kernel_ms": kern_ms,
+        },
+        "int_alu": {
+            "achieved": COUNTERS["int32_valu_per_config"] * achieved / 1e12 if valid else None,
+            "peak": INT_VALU_PEAK / 1e12,
+            "unit": "Tops/s",
+            "frac": COUNTERS["int32_valu_per_config"] * achieved / INT_VALU_PEAK if valid else None,
+            "int32_valu_per_config": COUNTERS["int32_valu_per_config"] if valid else None,
+            "basis": "rocprofv3 SQ_INSTS_VALU_INT32 x 64 lanes per configuration, times the event-timed rate",
         },
     }
     if not args.no_cpu_baseline:

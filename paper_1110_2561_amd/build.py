@@ -2,6 +2,9 @@
 
     python -m paper_1110_2561_amd.build
 
+It also builds microbench/lds_atomic, the microbenchmark of the LDS-atomic
+and integer-VALU rates the benchmark's roofline is reported against.
+
 The library is plain hipcc output: HIP kernels for gfx950 plus host C++,
 linked against the HIP runtime only.  Every HIP source is compiled with
 packed-FP32 instructions disabled.
@@ -56,6 +59,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the LDS-atomic / integer-VALU microbenchmark behind the roofline peaks
+    mb_src = os.path.join(HERE, "microbench", "lds_atomic.hip")
+    mb_exe = os.path.join(HERE, "microbench", "lds_atomic")
+    cmd = [hipcc, *HIP_FLAGS, "-x", "hip", mb_src, "-o", mb_exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"microbenchmark build failed: {' '.join(cmd)}\n{r.stderr}")
     return LIB
 
 
