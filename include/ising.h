@@ -76,6 +76,7 @@ typedef struct ising_tune {
   int32_t waves_per_block;      /* 1 .. 16 (64 lanes per wave) */
   int32_t replicas;             /* LDS histogram copies per block: 1, 2, 4, 8 or 16 */
   int32_t max_blocks;           /* grid cap */
+  int32_t prefix_bits;          /* N - k: log2 of the chunk count, used when inner_bits is 0 */
 } ising_tune;
 
 /* Opaque, immutable after creation.  Safe to use from several threads and
@@ -137,6 +138,54 @@ ising_status ising_moments(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int3
                            const double *h_dev, int32_t nh, double *logz_dev,
                            double *mean_E, double *mean_M, double *heat_capacity,
                            double *susceptibility, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many lattices of uneven size in one persistent launch.          */
+/* ------------------------------------------------------------------------ */
+
+/* Opaque batch plan: one plan per lattice (same rules as ising_plan_create,
+ * with one tile width and one coupling-class count shared by all members so
+ * a single kernel serves the batch) and a work list of (lattice, task) units
+ * ordered largest lattice first.  Immutable after creation, except for the
+ * device work counter: launches that use the same batch plan must not
+ * overlap in time (serialise them on one stream). */
+typedef struct ising_batch_plan ising_batch_plan;
+
+/* n lattices (host array of n descriptors, read during the call only);
+ * tune may be NULL (inner_bits is ignored; prefix_bits, tile_bits,
+ * replicas, waves_per_block and max_blocks apply to every member). */
+ising_status ising_batch_plan_create(const ising_lattice *lattices, int32_t n, const ising_tune *tune,
+                                     ising_batch_plan **plan);
+ising_status ising_batch_plan_destroy(ising_batch_plan *plan);
+
+/* Layout of the concatenated tables g_all: member i's dense [n_e[i]][n_m[i]]
+ * uint64 table starts at element offsets[i]; offsets has n + 1 entries, the
+ * last one being the total element count.  e_min[i] = -S_i.  Any output may
+ * be NULL; arrays are caller-owned host memory. */
+ising_status ising_batch_layout(const ising_batch_plan *plan, int64_t *offsets, int32_t *n_e, int32_t *n_m,
+                                int32_t *e_min, int32_t *n_spins);
+
+/* g(E, M) of every member into g_all (device, offsets[n] uint64,
+ * overwritten), in one persistent launch. */
+ising_status ising_batch_enumerate(const ising_batch_plan *plan, uint64_t *g_all_dev, void *stream);
+
+/* log Z and moments of every member on one (T, h) grid, as ising_moments;
+ * each output (any may be NULL) is [n][nT][nh] FP64 on the device. */
+ising_status ising_batch_moments(const ising_batch_plan *plan, const uint64_t *g_all_dev, const double *T_dev,
+                                 int32_t nT, const double *h_dev, int32_t nh, double *logz_dev,
+                                 double *mean_E, double *mean_M, double *heat_capacity,
+                                 double *susceptibility, void *stream);
+
+/* A captured HIP graph of {zero g_all, batched enumeration, batched
+ * moments} with the given buffers baked in (nT or nh = 0 leaves the moments
+ * out).  Replays reproduce ising_batch_enumerate + ising_batch_moments. */
+typedef struct ising_graph ising_graph;
+ising_status ising_batch_graph_create(const ising_batch_plan *plan, uint64_t *g_all_dev, const double *T_dev,
+                                      int32_t nT, const double *h_dev, int32_t nh, double *logz_dev,
+                                      double *mean_E, double *mean_M, double *heat_capacity,
+                                      double *susceptibility, ising_graph **graph);
+ising_status ising_graph_launch(const ising_graph *graph, void *stream);
+ising_status ising_graph_destroy(ising_graph *graph);
 
 /* Static text for a status code. */
 const char *ising_status_str(ising_status status);

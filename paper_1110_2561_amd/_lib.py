@@ -35,7 +35,7 @@ class ising_lattice(ctypes.Structure):
 
 class ising_tune(ctypes.Structure):
     _fields_ = [("inner_bits", i32), ("tile_bits", i32), ("waves_per_block", i32), ("replicas", i32),
-                ("max_blocks", i32)]
+                ("max_blocks", i32), ("prefix_bits", i32)]
 
 
 class IsingError(RuntimeError):
@@ -61,6 +61,17 @@ ising_enumerate = _sig("ising_enumerate", i32, vp, vp, vp)
 ising_enumerate_range = _sig("ising_enumerate_range", i32, vp, u64, u64, vp, vp)
 ising_logz = _sig("ising_logz", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp)
 ising_moments = _sig("ising_moments", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp)
+i64p = ctypes.POINTER(ctypes.c_int64)
+ising_batch_plan_create = _sig("ising_batch_plan_create", i32, ctypes.POINTER(ising_lattice), i32,
+                               ctypes.POINTER(ising_tune), ctypes.POINTER(vp))
+ising_batch_plan_destroy = _sig("ising_batch_plan_destroy", i32, vp)
+ising_batch_layout = _sig("ising_batch_layout", i32, vp, i64p, i32p, i32p, i32p, i32p)
+ising_batch_enumerate = _sig("ising_batch_enumerate", i32, vp, vp, vp)
+ising_batch_moments = _sig("ising_batch_moments", i32, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp)
+ising_batch_graph_create = _sig("ising_batch_graph_create", i32, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp,
+                                ctypes.POINTER(vp))
+ising_graph_launch = _sig("ising_graph_launch", i32, vp, vp)
+ising_graph_destroy = _sig("ising_graph_destroy", i32, vp)
 ising_status_str = _sig("ising_status_str", ctypes.c_char_p, i32)
 ising_last_error = _sig("ising_last_error", ctypes.c_char_p)
 ising_version = _sig("ising_version", ctypes.c_char_p)

@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from .lattice import Lattice
 
-__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_range", "log_z", "moments", "IsingError"]
+__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_range", "log_z", "moments", "IsingError",
+           "BatchPlan", "batch_enumerate", "batch_moments", "BatchGraph"]
 
 IsingError = _lib.IsingError
 
@@ -26,10 +27,11 @@ class Tune:
     waves_per_block: int = 0
     replicas: int = 0
     max_blocks: int = 0
+    prefix_bits: int = 0
 
     def _c(self):
         return _lib.ising_tune(self.inner_bits, self.tile_bits, self.waves_per_block, self.replicas,
-                               self.max_blocks)
+                               self.max_blocks, self.prefix_bits)
 
 
 def _stream_handle(stream) -> int | None:
@@ -136,3 +138,133 @@ def moments(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dic
                                   outs["mean_M"].data_ptr(), outs["heat_capacity"].data_ptr(),
                                   outs["susceptibility"].data_ptr(), _stream_handle(stream)))
     return outs
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+
+def _lattice_struct(lat: Lattice, keep: list):
+    bi = np.ascontiguousarray(lat.bond_i, dtype=np.int32)
+    bj = np.ascontiguousarray(lat.bond_j, dtype=np.int32)
+    bJ = np.ascontiguousarray(lat.bond_J, dtype=np.int32)
+    keep += [bi, bj, bJ]
+    p = _lib.i32p
+    return _lib.ising_lattice(int(lat.n_spins), int(bi.shape[0]), bi.ctypes.data_as(p), bj.ctypes.data_as(p),
+                              bJ.ctypes.data_as(p))
+
+
+class BatchPlan:
+    """Many lattices in one persistent launch (ising_batch_plan_create)."""
+
+    def __init__(self, lattices, tune: Tune | None = None):
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        keep: list = []
+        arr = (_lib.ising_lattice * n)(*[_lattice_struct(l, keep) for l in self.lattices])
+        handle = ctypes.c_void_p()
+        tn = tune._c() if tune is not None else None
+        _lib.check(_lib.ising_batch_plan_create(arr, n, ctypes.byref(tn) if tn is not None else None,
+                                                ctypes.byref(handle)))
+        self._h = handle
+        off = (ctypes.c_int64 * (n + 1))()
+        n_e, n_m, e_min, n_sp = ((ctypes.c_int32 * n)() for _ in range(4))
+        _lib.check(_lib.ising_batch_layout(self._h, off, n_e, n_m, e_min, n_sp))
+        self.offsets = np.array(off[:], dtype=np.int64)
+        self.n_e = np.array(n_e[:]); self.n_m = np.array(n_m[:]); self.e_min = np.array(e_min[:])
+        self.n_spins = np.array(n_sp[:])
+
+    def __len__(self):
+        return len(self.lattices)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def total_configs(self) -> int:
+        return int(sum(1 << int(n) for n in self.n_spins))
+
+    def new_tables(self, device="cuda") -> torch.Tensor:
+        return torch.empty(int(self.offsets[-1]), dtype=torch.uint64, device=device)
+
+    def table(self, g_all: torch.Tensor, i: int) -> torch.Tensor:
+        """Member i's [n_e][n_m] view of the concatenated tables."""
+        a, b = int(self.offsets[i]), int(self.offsets[i + 1])
+        return g_all[a:b].view(int(self.n_e[i]), int(self.n_m[i]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ising_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_all(plan: BatchPlan, g_all: torch.Tensor):
+    if not (g_all.is_cuda and g_all.dtype == torch.uint64 and g_all.is_contiguous()
+            and g_all.numel() == int(plan.offsets[-1])):
+        raise ValueError(f"g_all must be a contiguous CUDA uint64 tensor of {int(plan.offsets[-1])} elements")
+
+
+def batch_enumerate(plan: BatchPlan, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """g(E, M) of every member, concatenated (ising_batch_enumerate)."""
+    g = plan.new_tables() if out is None else out
+    _check_all(plan, g)
+    _lib.check(_lib.ising_batch_enumerate(plan.handle, g.data_ptr(), _stream_handle(stream)))
+    return g
+
+
+def _batch_outputs(plan: BatchPlan, Tt, ht, device):
+    shape = (len(plan), Tt.numel(), ht.numel())
+    return {k: torch.empty(shape, dtype=torch.float64, device=device)
+            for k in ("log_z", "mean_E", "mean_M", "heat_capacity", "susceptibility")}
+
+
+def batch_moments(plan: BatchPlan, g_all: torch.Tensor, T, h, stream=None) -> dict:
+    """log Z and moments of every member, each [n][len(T)][len(h)] (ising_batch_moments)."""
+    _check_all(plan, g_all)
+    Tt, ht = _grid(T, g_all.device), _grid(h, g_all.device)
+    outs = _batch_outputs(plan, Tt, ht, g_all.device)
+    _lib.check(_lib.ising_batch_moments(plan.handle, g_all.data_ptr(), Tt.data_ptr(), Tt.numel(), ht.data_ptr(),
+                                        ht.numel(), outs["log_z"].data_ptr(), outs["mean_E"].data_ptr(),
+                                        outs["mean_M"].data_ptr(), outs["heat_capacity"].data_ptr(),
+                                        outs["susceptibility"].data_ptr(), _stream_handle(stream)))
+    return outs
+
+
+class BatchGraph:
+    """A HIP graph of {zero, batched enumeration, batched moments} with its
+    buffers (ising_batch_graph_create); replay() launches it."""
+
+    def __init__(self, plan: BatchPlan, T, h, device="cuda"):
+        self.plan = plan
+        self.g_all = plan.new_tables(device)
+        self.T, self.h = _grid(T, device), _grid(h, device)
+        self.outs = _batch_outputs(plan, self.T, self.h, device)
+        handle = ctypes.c_void_p()
+        o = self.outs
+        _lib.check(_lib.ising_batch_graph_create(plan.handle, self.g_all.data_ptr(), self.T.data_ptr(),
+                                                 self.T.numel(), self.h.data_ptr(), self.h.numel(),
+                                                 o["log_z"].data_ptr(), o["mean_E"].data_ptr(),
+                                                 o["mean_M"].data_ptr(), o["heat_capacity"].data_ptr(),
+                                                 o["susceptibility"].data_ptr(), ctypes.byref(handle)))
+        self._h = handle
+
+    def replay(self, stream=None):
+        _lib.check(_lib.ising_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ising_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -23,9 +23,10 @@
 //     popcount of the spin word against its neighbour masks, and the D_i of
 //     tile spins coupled to it move by a plan constant.
 //   * Every configuration adds 1 to its (E, n_up) bin in an LDS histogram
-//     with R copies per block; lane l writes copy l mod R.  Copy-major words
-//     (bin * R + copy) and a bin-row stride that is a multiple of 4 keep the
-//     32 lanes one LDS cycle serves in distinct banks.  Counters are u32; the
+//     with R copies per block (lane_copy in walk.h).  Copy-major words
+//     (bin * R + copy), an even bin-row stride and the planner's placement of
+//     the lane-distinguishing spins keep the 32 lanes one LDS cycle serves in
+//     distinct banks.  Counters are u32; the
 //     block flushes them (sum over copies, 64-bit global atomics into the
 //     dense uint64 table) before any can reach 2^32, and at exit.
 //   * No HBM traffic beyond the final flush: the kernel is bound by the LDS
@@ -35,6 +36,7 @@
 #include <string>
 
 #include "internal.h"
+#include "walk.h"
 
 namespace ising {
 
@@ -44,164 +46,12 @@ namespace ising {
     if (e_ != hipSuccess) return fail(ISING_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// ---------------------------------------------------------------------------
-// device helpers
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void lds_count(char *hist, uint32_t byte_addr) {
-  __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(hist + byte_addr), 1u, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// One block of 2^TJ configurations: count the current one, then walk the
-// tile bits in Gray order.  In odd blocks the tile starts with its top bit
-// set (reflected code), so that bit's single flip goes down instead of up.
-template <int TJ, bool ODD>
-__device__ __forceinline__ void tile_walk(uint32_t &A, const int32_t (&D)[TJ], char *hist) {
-  lds_count(hist, A);
-#pragma unroll
-  for (int t = 1; t < (1 << TJ); ++t) {
-    const int b = __builtin_ctz(t);
-    const int gray = t ^ (t >> 1);
-    bool up = (gray >> b) & 1;
-    if (ODD && b == TJ - 1) up = !up;
-    A = up ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
-    lds_count(hist, A);
-  }
-}
-
-// Plan constants held in registers for the whole launch.  Per-site data sit
-// one site per lane (site b in lane b, N <= 64) and are fetched with
-// v_readlane at a wave-uniform index, so neither the chunk set-up nor the
-// walk issues a scalar memory load (whose wait would also drain the wave's
-// outstanding LDS atomics).
-template <int TJ, int NC>
-struct SiteTable {
-  uint32_t mlo[NC], mhi[NC];   // neighbour masks of the lane's site, per coupling class
-  int32_t hdeg;                // sum_c J_c deg_c of the lane's site
-  int32_t base;                // up_base of the lane's site
-  int32_t kmid[TJ];            // lane m: tile-delta changes when middle bit TJ + m flips up
-  int32_t jc[NC], step[NC];    // class couplings and byte steps (uniform)
-  int32_t n, k, e_base, estep, row_bytes, col_bytes;   // uniform
-
-  __device__ void load(const DevPlan *__restrict__ P, int lane) {
-    n = P->n;
-    k = P->inner;
-    e_base = P->e_base;
-    estep = P->estep;
-    row_bytes = P->W * P->R * 4;
-    col_bytes = P->R * 4;
-    const bool site = lane < n;
-    const int b = site ? lane : 0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const uint64_t m = site ? P->mask[b][c] : 0ull;
-      mlo[c] = uint32_t(m);
-      mhi[c] = uint32_t(m >> 32);
-      jc[c] = P->class_J[c];
-      step[c] = P->cls_step[c];
-    }
-    hdeg = site ? P->hdeg[b] : 0;
-    base = site ? P->up_base[b] : 0;
-    const bool mid = lane < k - TJ;
-#pragma unroll
-    for (int i = 0; i < TJ; ++i) kmid[i] = mid ? P->kmid[mid ? lane : 0][i] : 0;
-  }
-
-  // popcount(x & mask of site b, class c) for a wave-uniform b
-  __device__ __forceinline__ int32_t pop(int b, int c, uint32_t xlo, uint32_t xhi) const {
-    return __popc(xlo & uint32_t(__builtin_amdgcn_readlane(int(mlo[c]), b))) +
-           __popc(xhi & uint32_t(__builtin_amdgcn_readlane(int(mhi[c]), b)));
-  }
-
-  // local field h_b = sum_j J_bj s_j
-  __device__ __forceinline__ int32_t field(int b, uint32_t xlo, uint32_t xhi) const {
-    int32_t acc = 0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc += jc[c] * pop(b, c, xlo, xhi);
-    return 2 * acc - __builtin_amdgcn_readlane(hdeg, b);
-  }
-
-  // histogram byte-offset change when bit b flips up
-  __device__ __forceinline__ int32_t up_delta(int b, uint32_t xlo, uint32_t xhi) const {
-    int32_t acc = __builtin_amdgcn_readlane(base, b);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc -= step[c] * pop(b, c, xlo, xhi);
-    return acc;
-  }
-};
-
-// All 2^k configurations of one chunk (prefix bits fixed).
-template <int TJ, int NC>
-__device__ void walk_chunk(const SiteTable<TJ, NC> &st, uint64_t chunk, uint32_t rep, char *hist) {
-  const int k = st.k;
-  const uint64_t x0 = chunk << k;
-  const uint32_t x0lo = uint32_t(x0), x0hi = uint32_t(x0 >> 32);
-
-  // Full (E, n_up) of the first configuration: E = -(1/2) sum_i s_i h_i.
-  int32_t hs = 0;
-  for (int i = 0; i < st.n; ++i) {
-    const int32_t h = st.field(i, x0lo, x0hi);
-    hs += ((x0 >> i) & 1) ? h : -h;
-  }
-  const int32_t E0 = -(hs / 2);
-  const int32_t nup = __popcll(x0);
-  uint32_t A = uint32_t(((E0 - st.e_base) / st.estep) * st.row_bytes + nup * st.col_bytes) + rep * 4u;
-
-  // Up-flip address change of each tile spin (its neighbours are all outside
-  // the tile, so these stay fixed while only tile bits flip).
-  int32_t D[TJ];
-#pragma unroll
-  for (int i = 0; i < TJ; ++i) D[i] = st.up_delta(i, x0lo, x0hi);
-
-  const uint32_t nblk = 1u << (k - TJ);
-  for (uint32_t q = 0; q < nblk; ++q) {
-    if (q & 1)
-      tile_walk<TJ, true>(A, D, hist);
-    else
-      tile_walk<TJ, false>(A, D, hist);
-    if (q + 1 < nblk) {
-      // Gray step q -> q+1 of the middle bits flips bit TJ + ctz(q+1).
-      const uint32_t q1 = q + 1;
-      const int mm = __builtin_ctz(q1);
-      const bool up = (((q1 ^ (q1 >> 1)) >> mm) & 1u) != 0;
-      // current inner bits: tile at its end state, middle bits = gray(q)
-      const uint64_t inner = ((q & 1) ? 0ull : (1ull << (TJ - 1))) | (uint64_t(q ^ (q >> 1)) << TJ);
-      const int32_t dm = st.up_delta(TJ + mm, x0lo | uint32_t(inner), x0hi | uint32_t(inner >> 32));
-      A = up ? A + uint32_t(dm) : A - uint32_t(dm);
-#pragma unroll
-      for (int i = 0; i < TJ; ++i) {
-        const int32_t kv = __builtin_amdgcn_readlane(st.kmid[i], mm);
-        D[i] = up ? D[i] + kv : D[i] - kv;
-      }
-    }
-  }
-}
-
-// Sum the R copies of every compact bin, clear them, add to the dense table.
-__device__ void flush_hist(const DevPlan *__restrict__ P, uint32_t *h, unsigned long long *__restrict__ g) {
-  const int W = P->W, R = P->R;
-  const int bins = P->n_ec * W;
-  for (int b = threadIdx.x; b < bins; b += blockDim.x) {
-    unsigned long long s = 0;
-    for (int r = 0; r < R; ++r) {
-      s += h[b * R + r];
-      h[b * R + r] = 0;
-    }
-    const int e_idx = b / W, nu = b - e_idx * W;
-    if (s && nu < P->n_m) {
-      const int E = P->e_base + e_idx * P->estep;
-      atomicAdd(&g[size_t(E - P->e_min) * P->n_m + nu], s);
-    }
-  }
-}
-
 // Task t of this block covers chunks (task_lo + t) * blockDim.x + [0, blockDim.x),
 // one per thread; lanes whose chunk lies outside [chunk_lo, chunk_hi) idle.
 // Lanes l and l + 16 of a half-wave share LDS copy l mod 16; their chunks
-// differ in one prefix spin, so their n_up differ by one, and with a row
-// stride W = 0 (mod 4) their words fall in different banks (bank = 16 * (bin
-// mod 4) + copy on the 64-bank LDS).  All threads of a block run the
+// differ in one prefix spin, so their n_up differ by one, and with an even
+// row stride W their words fall in different banks (bank = 16 * (bin mod 2)
+// + copy on the 32-bank LDS).  All threads of a block run the
 // same number of tasks, so the barriers around periodic flushes are uniform.
 template <int TJ, int NC>
 __global__ __launch_bounds__(1024) void k_enumerate(const DevPlan *__restrict__ P, uint64_t chunk_lo,
@@ -209,14 +59,14 @@ __global__ __launch_bounds__(1024) void k_enumerate(const DevPlan *__restrict__ 
                                                     uint32_t flush_every, unsigned long long *__restrict__ g) {
   // Static (not dynamic) LDS: its base address is a compile-time constant, so
   // each histogram update is a single ds_add_u32 on the running address.
-  __shared__ __align__(16) uint32_t h32[kLdsBytes / 4];
+  __shared__ __align__(16) uint32_t h32[kHistBytes / 4];
   char *hist = reinterpret_cast<char *>(h32);
   const int words = P->n_ec * P->W * P->R;
   for (int w = threadIdx.x; w < words; w += blockDim.x) h32[w] = 0;
   __syncthreads();
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t rep = lane & uint32_t(P->R - 1);
-  SiteTable<TJ, NC> st;
+  const uint32_t rep = lane_copy(lane, P->R);
+  SiteTable<NC> st;
   st.load(P, int(lane));
   uint32_t since = 0;
   for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {

@@ -5,6 +5,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/ising.h"
 
@@ -16,6 +17,7 @@ constexpr int kMaxTile = 8;         // tile bits j (independent-set spins)
 constexpr int kMaxInner = 25;       // inner bits k (configurations per chunk 2^k)
 constexpr int kMaxMiddle = kMaxInner - 1;
 constexpr int kLdsBytes = 160 * 1024;
+constexpr int kHistBytes = kLdsBytes - 64;   // LDS histogram; the rest holds block control words
 constexpr int kWave = 64;
 constexpr int kMaxDevices = 64;
 
@@ -31,7 +33,7 @@ struct DevPlan {
   int32_t estep;         // every E lies on e_base + estep * Z
   int32_t e_base;        // lowest compact energy (>= -S_eff)
   int32_t n_ec;          // compact energy rows
-  int32_t W;             // compact row stride: n + 1 rounded up to a multiple of 4
+  int32_t W;             // compact row stride: least even W >= n + 1
   int32_t R;             // LDS replicas (power of two)
   int32_t e_min;         // dense table: e_min = -S
   int32_t n_m;           // dense table columns = n + 1
@@ -69,7 +71,46 @@ struct ising_plan {
 };
 
 namespace ising {
+
+// One unit of batched work: task `task` (chunks task*block .. +block) of member `inst`.
+struct BatchUnit {
+  int32_t inst;
+  int32_t pad;
+  uint64_t task;
+};
+
+// Per-member launch data of a batch.
+struct BatchMember {
+  uint64_t n_chunks;
+  int64_t offset;        // first element of the member's table in g_all
+  uint32_t flush_every;  // tasks between LDS flushes
+  int32_t n_e, n_m, e_min, n_spins;
+  int32_t pad;
+};
+
 void set_error(const std::string &msg);
+// plan_create with every member forced to `min_classes` or more coupling classes
+// exact_tile: tune.tile_bits must be met exactly (else it is an upper bound)
+ising_status plan_create_internal(const ising_lattice *lat, const ising_tune *tune, int min_classes,
+                                  ising_plan **out, bool exact_tile = true);
 ising_status fail(ising_status st, const std::string &msg);
 const void *plan_device_constants(ising_plan *plan, int device, ising_status *st);
 }  // namespace ising
+
+struct ising_batch_plan {
+  int32_t n = 0;
+  int32_t n_classes = 0;
+  int32_t waves_per_block = 16;
+  int32_t max_blocks = 0;
+  std::vector<ising_plan *> members;      // owned
+  std::vector<ising::BatchMember> meta;
+  std::vector<ising::BatchUnit> units;
+  int64_t total_elems = 0;
+  std::mutex mu;
+  struct Dev {
+    void *plans = nullptr;    // DevPlan[n]
+    void *meta = nullptr;     // BatchMember[n]
+    void *units = nullptr;    // BatchUnit[units]
+    void *counter = nullptr;  // uint32 work counter
+  } dev[ising::kMaxDevices];
+};

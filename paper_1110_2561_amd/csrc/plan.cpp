@@ -50,8 +50,54 @@ extern "C" const char *ising_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" const char *ising_version(void) { return "libising 0.1 (gfx950)"; }
 
+// Lanes l of a wave enumerate chunks base + l, so chunk bits 0..5 (plan bits
+// k..k+5) tell a wave's lanes apart.  Lanes a, b that share an LDS copy
+// (a = b mod R) hold configurations that differ by flipping the spin set F on
+// the bits of a ^ b.  When their n_up agree (equal popcounts) they hit the
+// same LDS word whenever their energies agree as well.  Flipping F changes
+// the energy by 2 * sum_{bonds crossing F} J s_i s_j, which is 2 * (number of
+// odd couplings crossing F) modulo 4, and that number has the parity of
+// sum_{i in F} d_i, d_i being the count of odd couplings at spin i.  So when
+// estep = 2 (mod 4) the two energy indices have different parity, and never
+// agree, if the spins of F hold an odd number of odd d_i.  This picks the
+// parity pattern of bits k..k+5 that does so for the most such lane pairs,
+// among the patterns the prefix spins can supply, and moves matching prefix
+// spins to those bits.  The order of prefix spins is otherwise free.
+static void place_lane_spins(int n, int k, int R, const std::vector<int64_t> &J, int32_t *site_of_bit) {
+  int want[64] = {0};  // flip patterns of same-copy lane pairs with equal n_up
+  for (int a = 0; a < 64; ++a)
+    for (int b = a + 1; b < 64; ++b)
+      if ((a & (R - 1)) == (b & (R - 1)) && __builtin_popcount(a) == __builtin_popcount(b)) ++want[a ^ b];
+  std::vector<int32_t> odd_sites, even_sites;  // prefix spins by parity of d_i
+  for (int b = k; b < n; ++b) {
+    const int i = site_of_bit[b];
+    int d = 0;
+    for (int j = 0; j < n; ++j) d += int(J[size_t(i) * n + j] & 1);
+    (d & 1 ? odd_sites : even_sites).push_back(i);
+  }
+  int best = -1, best_p = 0;
+  for (int p = 0; p < 64; ++p) {
+    const int w = __builtin_popcount(p);
+    if (w > int(odd_sites.size()) || 6 - w > int(even_sites.size())) continue;
+    int sc = 0;
+    for (int f = 1; f < 64; ++f)
+      if (__builtin_popcount(f & p) & 1) sc += want[f];
+    if (sc > best) { best = sc; best_p = p; }
+  }
+  size_t io = 0, ie = 0;
+  int32_t *dst = site_of_bit + k;
+  for (int b = 0; b < 6; ++b) *dst++ = (best_p >> b & 1) ? odd_sites[io++] : even_sites[ie++];
+  while (io < odd_sites.size()) *dst++ = odd_sites[io++];
+  while (ie < even_sites.size()) *dst++ = even_sites[ie++];
+}
+
 extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_tune *tune,
                                           ising_plan **out) {
+  return ising::plan_create_internal(lat, tune, 1, out);
+}
+
+ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_tune *tune, int min_classes,
+                                         ising_plan **out, bool exact_tile) {
   if (!out) return fail(ISING_EINVAL, "plan output pointer is NULL");
   *out = nullptr;
   if (!lat) return fail(ISING_EINVAL, "lattice is NULL");
@@ -64,7 +110,8 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   ising_tune tn{};
   if (tune) tn = *tune;
   if (tn.inner_bits < 0 || tn.inner_bits > kMaxInner || tn.tile_bits < 0 || tn.tile_bits > kMaxTile ||
-      tn.waves_per_block < 0 || tn.waves_per_block > 16 || tn.max_blocks < 0 ||
+      tn.waves_per_block < 0 || tn.waves_per_block > 16 || tn.max_blocks < 0 || tn.prefix_bits < 0 ||
+      tn.prefix_bits > kMaxSpins ||
       (tn.replicas != 0 && (tn.replicas > 16 || (tn.replicas & (tn.replicas - 1)))))
     return fail(ISING_EINVAL, "tune values out of range");
 
@@ -97,7 +144,7 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
       E_ref -= v;  // all spins up: every pair contributes -J
       if (std::find(classes.begin(), classes.end(), v) == classes.end()) classes.push_back(v);
     }
-  if ((int)classes.size() > kMaxClasses)
+  if ((int)classes.size() > kMaxClasses || min_classes > kMaxClasses)
     return fail(ISING_EUNSUPPORTED, std::to_string(classes.size()) +
                                         " distinct merged couplings (at most 8 supported)");
   std::sort(classes.begin(), classes.end());
@@ -121,14 +168,15 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   if (!estep) estep = 1;
   const int64_t e_base = E_ref - estep * floor_div(E_ref + S_eff, estep);
   const int64_t n_ec = (S_eff - e_base) / estep + 1;
-  // Row stride: n + 1 columns rounded up to a multiple of 4, so that a bin's
-  // LDS bank group (bin mod 4) follows n_up mod 4 (see enumerate.hip).
-  const int W = (n + 1 + 3) & ~3;
+  // Row stride: the least even W >= n + 1.  With 16 copies a bin's bank on
+  // the 32-bank LDS is 16 * (bin mod 2) + copy, and bin mod 2 = n_up mod 2
+  // for even W, so lanes l and l + 16 (n_up one apart) never collide.
+  const int W = (n + 2) & ~1;
 
   // ---- histogram replicas that fit the LDS ----
   int R = tn.replicas ? tn.replicas : 16;
-  while (R > 1 && n_ec * W * R * 4 > kLdsBytes) R >>= 1;
-  if (n_ec * W * R * 4 > kLdsBytes)
+  while (R > 1 && n_ec * W * R * 4 > kHistBytes) R >>= 1;
+  if (n_ec * W * R * 4 > kHistBytes)
     return fail(ISING_ERANGE, "compact histogram of " + std::to_string(n_ec) + " x " + std::to_string(W) +
                                   " bins exceeds the 160 KB LDS");
   const int wpb = tn.waves_per_block ? tn.waves_per_block : 16;
@@ -136,21 +184,35 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   // array, so histogram addresses need no base add): one block per CU.
   const int bpc = 1;
 
-  // ---- tile: a greedy independent set (no merged coupling between members) ----
+  // ---- tile: an independent set (no merged coupling between members), by
+  // the minimum-degree greedy rule: take a site of least remaining degree,
+  // drop it and its neighbours, repeat ----
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degree[a] > degree[b]; });
   std::vector<int> tile;
   const int tile_want = tn.tile_bits ? tn.tile_bits : kMaxTile;
-  for (int s : order) {
-    if ((int)tile.size() >= tile_want) break;
-    bool ok = true;
-    for (int t : tile)
-      if (J[size_t(s) * n + t]) { ok = false; break; }
-    if (ok) tile.push_back(s);
+  {
+    std::vector<char> alive(n, 1);
+    std::vector<int> rem(degree);
+    while ((int)tile.size() < tile_want) {
+      int best = -1;
+      for (int s2 = 0; s2 < n; ++s2)
+        if (alive[s2] && (best < 0 || rem[s2] < rem[best])) best = s2;
+      if (best < 0) break;
+      tile.push_back(best);
+      std::vector<int> gone{best};
+      for (int j = 0; j < n; ++j)
+        if (alive[j] && j != best && J[size_t(best) * n + j]) gone.push_back(j);
+      for (int g2 : gone) {
+        alive[g2] = 0;
+        for (int j = 0; j < n; ++j)
+          if (alive[j] && J[size_t(g2) * n + j]) --rem[j];
+      }
+    }
   }
   const int TJ = std::max(1, std::min<int>((int)tile.size(), n));
-  if (tn.tile_bits && TJ != tn.tile_bits)
+  if (exact_tile && tn.tile_bits && TJ != tn.tile_bits)
     return fail(ISING_EINVAL, "no independent set of " + std::to_string(tn.tile_bits) + " spins");
 
   // ---- inner bits k: enough chunks for several tasks per block ----
@@ -158,12 +220,13 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   if (tn.inner_bits) {
     k = tn.inner_bits;
     if (k < TJ || k > n) return fail(ISING_EINVAL, "inner_bits must lie in [tile_bits, n_spins]");
+  } else if (tn.prefix_bits) {
+    k = std::max(TJ, std::min(std::min(n - tn.prefix_bits, n), kMaxInner));
   } else {
-    // ~16 tasks per block on 256 CUs: chunk costs vary (ordered prefixes
-    // collide more in the LDS), and many short tasks per block even out
-    // the finishing times of the blocks.
+    // ~4 tasks per block on 256 CUs: enough to even out the blocks'
+    // finishing times, with chunks large enough to amortise their set-up.
     const int lanes_log2 = 8 /* 256 CUs */ + (bpc > 1 ? 1 : 0) + 6 + (31 - __builtin_clz(unsigned(wpb)));
-    k = n - (lanes_log2 + 4);
+    k = n - (lanes_log2 + 2);
     k = std::max(TJ, std::min(std::min(k, n), kMaxInner));
   }
   // every u32 LDS counter must stay below 2^32 between flushes:
@@ -184,6 +247,7 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   for (int t = 0; t < TJ; ++t) { p->site_of_bit[bit++] = tile[t]; used[tile[t]] = 1; }
   for (int s : order)
     if (!used[s]) { p->site_of_bit[bit++] = s; used[s] = 1; }
+  if (estep % 4 == 2 && n - k >= 6 && R >= 2) place_lane_spins(n, k, R, J, p->site_of_bit);
   for (int b = 0; b < n; ++b) p->bit_of_site[p->site_of_bit[b]] = b;
 
   p->n_spins = n;
@@ -200,7 +264,7 @@ extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_
   d.inner = k;
   d.tile = TJ;
   d.n_classes = 1;
-  while (d.n_classes < (int)classes.size()) d.n_classes *= 2;   // kernels exist for 1, 2, 4, 8
+  while (d.n_classes < (int)classes.size() || d.n_classes < min_classes) d.n_classes *= 2;  // kernels: 1, 2, 4, 8
   d.estep = (int32_t)estep;
   d.e_base = (int32_t)e_base;
   d.n_ec = (int32_t)n_ec;

@@ -56,15 +56,11 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
   return v;
 }
 
-__global__ __launch_bounds__(kThermoThreads) void k_thermo(
-    const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
-    const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
-    double *__restrict__ logz, double *__restrict__ mean_E, double *__restrict__ mean_M,
-    double *__restrict__ heat, double *__restrict__ susc) {
-  __shared__ double sh[24];
-  const int pt = blockIdx.x;
-  const int ia = pt / nh, ib = pt - ia * nh;
-  const double T = Tg[ia], h = hg[ib];
+// All outputs of one (T, h) point of one table, written at index pt.
+__device__ void thermo_point(const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
+                             double T, double h, int pt, double *__restrict__ logz, double *__restrict__ mean_E,
+                             double *__restrict__ mean_M, double *__restrict__ heat, double *__restrict__ susc,
+                             double *sh) {
   const int bins = n_e * n_m;
   const bool want_moments = mean_E || mean_M || heat || susc;
   if (!(T > 0.0) || !isfinite(T) || !isfinite(h)) {
@@ -137,6 +133,47 @@ __global__ __launch_bounds__(kThermoThreads) void k_thermo(
     if (heat) heat[pt] = vh / z * inv_T * inv_T;
     if (susc) susc[pt] = vm / z * inv_T;
   }
+}
+
+__global__ __launch_bounds__(kThermoThreads) void k_thermo(
+    const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
+    const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
+    double *__restrict__ logz, double *__restrict__ mean_E, double *__restrict__ mean_M,
+    double *__restrict__ heat, double *__restrict__ susc) {
+  __shared__ double sh[24];
+  const int pt = blockIdx.x;
+  const int ia = pt / nh, ib = pt - ia * nh;
+  thermo_point(g, n_e, n_m, e_min, n_spins, Tg[ia], hg[ib], pt, logz, mean_E, mean_M, heat, susc, sh);
+}
+
+// Batched: block (pt, member) evaluates point pt of member `member`; outputs
+// are [member][nT][nh].
+__global__ __launch_bounds__(kThermoThreads) void k_batch_thermo(
+    const unsigned long long *__restrict__ g_all, const BatchMember *__restrict__ meta,
+    const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
+    double *__restrict__ logz, double *__restrict__ mean_E, double *__restrict__ mean_M,
+    double *__restrict__ heat, double *__restrict__ susc) {
+  __shared__ double sh[24];
+  const int pt = blockIdx.x, member = blockIdx.y;
+  const int ia = pt / nh, ib = pt - ia * nh;
+  const BatchMember mb = meta[member];
+  const int out = member * nT * nh + pt;
+  thermo_point(g_all + mb.offset, mb.n_e, mb.n_m, mb.e_min, mb.n_spins, Tg[ia], hg[ib], out, logz, mean_E,
+               mean_M, heat, susc, sh);
+}
+
+ising_status batch_thermo_launch(const BatchMember *meta_dev, int n_members, const uint64_t *g_all,
+                                 const double *T_dev, int32_t nT, const double *h_dev, int32_t nh, double *logz,
+                                 double *mE, double *mM, double *C, double *chi, hipStream_t stream) {
+  if (nT == 0 || nh == 0 || n_members == 0) return ISING_OK;
+  if (!T_dev || !h_dev) return fail(ISING_EINVAL, "T_dev or h_dev is NULL");
+  if (int64_t(nT) * nh > 65535 * 64) return fail(ISING_EINVAL, "grid too large");
+  hipLaunchKernelGGL(k_batch_thermo, dim3(unsigned(nT * nh), unsigned(n_members)), dim3(kThermoThreads), 0, stream,
+                     reinterpret_cast<const unsigned long long *>(g_all), meta_dev, T_dev, nT, h_dev, nh, logz, mE,
+                     mM, C, chi);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_batch_thermo launch: ") + hipGetErrorString(e));
+  return ISING_OK;
 }
 
 static ising_status thermo_launch(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min, int32_t n_spins,

@@ -127,3 +127,21 @@ def test_product_never_imports_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
                 assert "liboracle" not in src, f
+
+
+def test_batch_plan_layout_on_cpu():
+    from paper_1110_2561_amd.api import BatchPlan, Tune
+    lats = [L.square_torus(4, 4), L.ring(7), L.cubic_torus(3, L.choice_couplings(81, 1)), L.Lattice(1, [], [], [])]
+    b = BatchPlan(lats, Tune(prefix_bits=10))
+    sizes = [(2 * l.abs_coupling_sum + 1) * (l.n_spins + 1) for l in lats]
+    assert b.offsets.tolist() == [0] + np.cumsum(sizes).tolist()
+    assert b.n_spins.tolist() == [16, 7, 27, 1]
+    assert b.total_configs == sum(1 << l.n_spins for l in lats)
+
+
+def test_batch_plan_errors_name_the_member():
+    from paper_1110_2561_amd.api import BatchPlan, IsingError
+    with pytest.raises(IsingError):
+        BatchPlan([])
+    with pytest.raises(IsingError, match="member 1"):
+        BatchPlan([L.ring(5), L.Lattice(3, [0], [0], [1])])

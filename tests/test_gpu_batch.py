@@ -1,0 +1,143 @@
+"""Batched persistent enumeration, batched moments and graph replay, against
+the oracle (bit-exact tables, FP64 moments within 1e-12)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import closed_forms, native, thermo
+from paper_1110_2561_amd import lattice as L
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1110_2561_amd import api as A
+    return A
+
+
+def _bf(lat):
+    return native.count_all(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J)
+
+
+def _tri(N, Lx, seed):
+    base = L.triangular_free(N, Lx)
+    return L.triangular_free(N, Lx, L.choice_couplings(base.n_bonds, seed))
+
+
+def small_batch():
+    return [
+        L.square_torus(4, 5, L.choice_couplings(40, 1)),
+        L.Lattice(1, [], [], []),
+        L.ring(9, L.pm_couplings(9, 3)),
+        _tri(17, 4, 5),
+        L.cubic_torus(2, L.choice_couplings(24, 6)),
+        L.random_bond_lattice(13, 40, 7),
+        L.Lattice(6, [], [], []),
+        L.square_torus(3, 6),
+        L.random_bond_lattice(20, 35, 9, values=(-1, 1)),
+        L.square_torus(4, 4),
+        _tri(19, 5, 11),
+        L.Lattice(3, [0, 1], [1, 2], [2, -2]),
+    ]
+
+
+@pytest.mark.parametrize("tune", [None, {"prefix_bits": 4}, {"prefix_bits": 12, "replicas": 4},
+                                  {"max_blocks": 3, "waves_per_block": 4}, {"tile_bits": 2}],
+                         ids=["default", "pb4", "pb12-r4", "3blocks", "tile2"])
+def test_small_batch_bit_exact(api, tune):
+    lats = small_batch()
+    plan = api.BatchPlan(lats, api.Tune(**tune) if tune else None)
+    g = api.batch_enumerate(plan)
+    torch.cuda.synchronize()
+    g_host = g.cpu()
+    for i, lat in enumerate(lats):
+        print(f"member {i}: {lat.kind} N={lat.n_spins}", flush=True)
+        np.testing.assert_array_equal(plan.table(g_host, i).numpy(), _bf(lat))
+
+
+def test_batch256_parity(api):
+    lats = L.workload("batch256")["lattices"]
+    plan = api.BatchPlan(lats)
+    g = api.batch_enumerate(plan)
+    torch.cuda.synchronize()
+    g_host = g.cpu()
+    tri_small = sorted([i for i, l in enumerate(lats) if l.kind == "triangular_free"],
+                       key=lambda i: lats[i].n_spins)[:6]
+    cubes = [i for i, l in enumerate(lats) if l.kind == "cubic_torus"][:2]
+    for i, lat in enumerate(lats):
+        t = plan.table(g_host, i).numpy()
+        N = lat.n_spins
+        # properties that hold at any size
+        assert int(t.sum()) == 1 << N, i
+        np.testing.assert_array_equal(t.sum(axis=0).astype(object), closed_forms.binomial_marginal(N))
+        np.testing.assert_array_equal(t, t[:, ::-1])
+        # the oracle wherever it finishes in seconds
+        if lat.kind == "square_torus":
+            np.testing.assert_array_equal(t, native.tm_torus(*L.torus_coupling_grids(lat)))
+        elif i in tri_small or i in cubes:
+            print(f"member {i}: {lat.kind} N={N} vs brute force", flush=True)
+            np.testing.assert_array_equal(t, _bf(lat))
+
+
+def test_batch_matches_single_lattice_path(api):
+    lats = L.workload("batch256")["lattices"][::7]
+    plan = api.BatchPlan(lats)
+    g = api.batch_enumerate(plan).cpu()
+    for i, lat in enumerate(lats):
+        p1 = api.Plan(lat)
+        single = api.enumerate_g(p1).cpu()
+        assert torch.equal(plan.table(g, i), single), i
+
+
+def test_batch_moments_match_oracle(api):
+    lats = small_batch()
+    plan = api.BatchPlan(lats)
+    T = np.linspace(0.5, 5.0, 16)
+    h = np.array([-0.5, 0.0, 0.25])
+    refs = [_bf(l) for l in lats]
+    # evaluate on the oracle's tables so only the FP64 path differs
+    flat = np.concatenate([r.reshape(-1) for r in refs])
+    g = torch.from_numpy(flat.view(np.int64)).view(torch.uint64).cuda()
+    out = api.batch_moments(plan, g, T, h)
+    torch.cuda.synchronize()
+    for i, lat in enumerate(lats):
+        S, N = lat.abs_coupling_sum, lat.n_spins
+        lz = thermo.log_z(refs[i], -S, N, T, h)
+        mE, mM, C, chi = thermo.moments(refs[i], -S, N, T, h)
+        np.testing.assert_allclose(out["log_z"][i].cpu().numpy(), lz, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(out["mean_E"][i].cpu().numpy(), mE, rtol=1e-12, atol=1e-12 * max(S, 1))
+        np.testing.assert_allclose(out["mean_M"][i].cpu().numpy(), mM, rtol=1e-12, atol=1e-12 * N)
+        np.testing.assert_allclose(out["heat_capacity"][i].cpu().numpy(), C, rtol=1e-11, atol=1e-300)
+        np.testing.assert_allclose(out["susceptibility"][i].cpu().numpy(), chi, rtol=1e-11, atol=1e-300)
+
+
+def test_graph_replays_equal_eager(api):
+    lats = L.workload("batch256")["lattices"]
+    plan = api.BatchPlan(lats)
+    T = np.linspace(0.5, 5.0, 64)
+    h = np.array([0.0, 0.1, 0.5])
+    eager_g = api.batch_enumerate(plan)
+    eager = api.batch_moments(plan, eager_g, T, h)
+    torch.cuda.synchronize()
+    graph = api.BatchGraph(plan, T, h)
+    for rep in range(3):
+        graph.g_all.fill_(7)                       # stale contents must be overwritten
+        for v in graph.outs.values():
+            v.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(graph.g_all.cpu(), eager_g.cpu()), rep
+        for k, v in eager.items():
+            assert torch.equal(torch.nan_to_num(graph.outs[k], 1.5).cpu(), torch.nan_to_num(v, 1.5).cpu()), (rep, k)
+        # eager work between replays
+        api.batch_enumerate(plan, out=eager_g)
+        torch.cuda.synchronize()
+
+
+def test_batch_errors(api):
+    with pytest.raises(api.IsingError):
+        api.BatchPlan([])
+    with pytest.raises(api.IsingError, match="member 1"):
+        api.BatchPlan([L.ring(5), L.Lattice(3, [0], [0], [1])])
