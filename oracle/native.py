@@ -42,6 +42,9 @@ def _load():
             lib.oracle_count_range.restype = ctypes.c_int
             lib.oracle_tm_torus.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int, u64p]
             lib.oracle_tm_torus.restype = ctypes.c_int
+            lib.oracle_bond_split.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, ctypes.c_int,
+                                              u64p, u64p]
+            lib.oracle_bond_split.restype = ctypes.c_int
             _lib = lib
         return _lib
 
@@ -107,3 +110,22 @@ def tm_torus(Jh, Jv, n_threads: int | None = None) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle_tm_torus failed ({rc})")
     return g
+
+
+def bond_split(n_spins: int, bond_i, bond_j, bond_J, n_threads: int | None = None):
+    """(g, gp): g as count_all, and gp [n_bonds][2S+1][N+1] with gp[b][E][n_up]
+    the number of configurations in that bin whose bond-b spins agree."""
+    lib = _load()
+    bi, pbi = _i32(bond_i)
+    bj, pbj = _i32(bond_j)
+    bJ, pbJ = _i32(bond_J)
+    S = int(np.abs(bJ.astype(np.int64)).sum())
+    nb = int(bi.shape[0])
+    g = np.zeros((2 * S + 1, n_spins + 1), dtype=np.uint64)
+    gp = np.zeros((max(nb, 1), 2 * S + 1, n_spins + 1), dtype=np.uint64)
+    rc = lib.oracle_bond_split(int(n_spins), nb, pbi, pbj, pbJ, int(n_threads or default_threads()),
+                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                               gp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    if rc != 0:
+        raise ValueError(f"oracle_bond_split failed ({rc})")
+    return g, gp[:nb]

@@ -19,12 +19,15 @@
  * s_u = +1.  n_up = popcount(c), M = 2 n_up - N.  Output table g is dense,
  * row-major [2S+1][N+1], row E + S, column n_up, S = sum_b |J_b|.
  *
- * Two independent exact counts live here:
+ * Three exact counts live here:
  *   oracle_count_range : the definition written out (loop over configurations,
  *                        loop over bonds), for an index range of configurations;
  *   oracle_tm_torus    : a row-to-row transfer-matrix count for square tori with
  *                        per-bond couplings (a different algorithm, used to pin
- *                        the brute force and to reach the 6x6 / 8x5 sizes).
+ *                        the brute force and to reach the 6x6 / 8x5 sizes);
+ *   oracle_bond_split  : g together with, for every bond, the count of the
+ *                        configurations of each (E, n_up) whose two spins agree
+ *                        (the statistics behind derivatives in the couplings).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -222,6 +225,89 @@ int oracle_tm_torus(int Lx, int Ly, const int32_t *Jh, const int32_t *Jv,
     }
   }
   for (int t = 0; t < made; ++t) free(jobs[t].table);
+  free(jobs); free(th);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Bond-resolved counts.                                                    */
+/* ---------------------------------------------------------------------- */
+/* H of Eq. (1) depends on the coupling of bond b only through -J_b s_i s_j,
+ * so derivatives in J_b need, per (E, M), how many configurations have
+ * s_i s_j = +1 on that bond.  gp[b][E + S][n_up] counts them (the rest of the
+ * bin, g - gp, has s_i s_j = -1).  Same loops as the brute force above. */
+
+typedef struct {
+  int n, nb;
+  const int32_t *bi, *bj, *bJ;
+  int64_t S;
+  uint64_t lo, hi;
+  uint64_t *table; /* private g   [2S+1][n+1]      */
+  uint64_t *split; /* private gp  [nb][2S+1][n+1]  */
+  unsigned char *agree;
+} split_job;
+
+static void *split_worker(void *arg) {
+  split_job *jb = (split_job *)arg;
+  const int nm = jb->n + 1;
+  const size_t cells = (size_t)(2 * jb->S + 1) * (size_t)nm;
+  for (uint64_t c = jb->lo; c < jb->hi; ++c) {
+    int64_t e = 0;
+    for (int b = 0; b < jb->nb; ++b) {
+      const int64_t si = ((c >> jb->bi[b]) & 1u) ? 1 : -1;
+      const int64_t sj = ((c >> jb->bj[b]) & 1u) ? 1 : -1;
+      e -= (int64_t)jb->bJ[b] * si * sj;
+      jb->agree[b] = (unsigned char)(si == sj);
+    }
+    int up = 0;
+    for (int u = 0; u < jb->n; ++u) up += (int)((c >> u) & 1u);
+    const size_t cell = (size_t)(e + jb->S) * nm + up;
+    jb->table[cell] += 1;
+    for (int b = 0; b < jb->nb; ++b)
+      if (jb->agree[b]) jb->split[(size_t)b * cells + cell] += 1;
+  }
+  return NULL;
+}
+
+/* g (overwritten) and gp (overwritten) over all 2^n configurations. */
+int oracle_bond_split(int n, int nb, const int32_t *bi, const int32_t *bj, const int32_t *bJ,
+                      int n_threads, uint64_t *g, uint64_t *gp) {
+  if (n < 1 || n > 40 || nb < 0 || n_threads < 1 || !g || (nb > 0 && !gp)) return -1;
+  int64_t S = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (bi[b] < 0 || bi[b] >= n || bj[b] < 0 || bj[b] >= n) return -2;
+    S += bJ[b] < 0 ? -(int64_t)bJ[b] : bJ[b];
+  }
+  const uint64_t total = (uint64_t)1 << n;
+  const size_t cells = (size_t)(2 * S + 1) * (size_t)(n + 1);
+  if ((uint64_t)n_threads > total) n_threads = (int)total;
+  split_job *jobs = (split_job *)calloc((size_t)n_threads, sizeof(split_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+  if (!jobs || !th) { free(jobs); free(th); return -4; }
+  const uint64_t per = total / (uint64_t)n_threads, rem = total % (uint64_t)n_threads;
+  uint64_t lo = 0;
+  int rc = 0, made = 0;
+  for (int t = 0; t < n_threads; ++t) {
+    const uint64_t len = per + ((uint64_t)t < rem ? 1 : 0);
+    jobs[t] = (split_job){n, nb, bi, bj, bJ, S, lo, lo + len,
+                          (uint64_t *)calloc(cells, sizeof(uint64_t)),
+                          (uint64_t *)calloc(cells * (size_t)(nb > 0 ? nb : 1), sizeof(uint64_t)),
+                          (unsigned char *)calloc((size_t)(nb > 0 ? nb : 1), 1)};
+    made = t + 1;
+    if (!jobs[t].table || !jobs[t].split || !jobs[t].agree) { rc = -4; break; }
+    lo += len;
+  }
+  if (rc == 0) {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, split_worker, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    memset(g, 0, cells * sizeof(uint64_t));
+    if (nb > 0) memset(gp, 0, cells * (size_t)nb * sizeof(uint64_t));
+    for (int t = 0; t < n_threads; ++t) {
+      for (size_t k = 0; k < cells; ++k) g[k] += jobs[t].table[k];
+      for (size_t k = 0; k < cells * (size_t)nb; ++k) gp[k] += jobs[t].split[k];
+    }
+  }
+  for (int t = 0; t < made; ++t) { free(jobs[t].table); free(jobs[t].split); free(jobs[t].agree); }
   free(jobs); free(th);
   return rc;
 }
