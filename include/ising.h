@@ -140,6 +140,55 @@ ising_status ising_moments(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int3
                            double *susceptibility, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Derivatives of log Z (for automatic differentiation).                    */
+/* ------------------------------------------------------------------------ */
+
+/* First and second derivatives of log Z(T, h) of Eq. (2), each [nT][nh] FP64
+ * on the device (any output may be NULL), from differentiating the sum over
+ * configurations with H = E - h M:
+ *   d_T  = <H>/T^2,   d_h  = <M>/T,
+ *   d_TT = Var(H)/T^4 - 2 <H>/T^3,
+ *   d_Th = (Cov(H, M)/T - <M>)/T^2,   d_hh = Var(M)/T^2.
+ * Inputs and error behaviour as ising_moments. */
+ising_status ising_logz_derivatives(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min,
+                                    int32_t n_spins, const double *T_dev, int32_t nT,
+                                    const double *h_dev, int32_t nh, double *logz_dev,
+                                    double *d_T, double *d_h, double *d_TT, double *d_Th,
+                                    double *d_hh, void *stream);
+
+/* Per-configuration weights of a loss L = sum_{a,b} grad[a][b] log Z(T_a, h_b):
+ * every configuration of bin (E, M) contributes
+ *   W(E, M) = sum_{a,b} grad[a][b] exp(-(E - h_b M)/T_a - logz[a][b]) / T_a
+ * (its Boltzmann probability at (T_a, h_b) times grad / T_a) to
+ * dL/dJ_b = sum over configurations of W s_i s_j (Eq. (1): H depends on J_b
+ * through -J_b s_i s_j).  g_dev, n_e, n_m, e_min, n_spins describe the
+ * table as in ising_logz; logz_dev and grad_dev are [nT][nh] FP64 (logz as
+ * returned by ising_logz for the same table and grid); W_dev receives the
+ * dense [n_e][n_m] FP64 table (overwritten; 0 on empty bins). */
+ising_status ising_bin_weights(const uint64_t *g_dev, int32_t n_e, int32_t n_m, int32_t e_min,
+                               int32_t n_spins, const double *T_dev, int32_t nT,
+                               const double *h_dev, int32_t nh, const double *logz_dev,
+                               const double *grad_dev, double *W_dev, void *stream);
+
+/* Bytes of device workspace ising_bond_backward needs for this plan (on the
+ * current device).  Fails with ISING_EUNSUPPORTED when the backward cannot
+ * run for this lattice (more than 512 distinct bond pairs, or a weight table
+ * too large for the LDS); the message says which. */
+ising_status ising_bond_workspace(const ising_plan *plan, size_t *bytes);
+
+/* dJ[b] = sum over all 2^N configurations of W(E, M) s_i s_j for every input
+ * bond b = (i, j) of the plan's lattice, in input order (repeated pairs get
+ * the same value).  With W from ising_bin_weights this is dL/dJ_b.  The
+ * enumeration is recomputed (nothing from the forward pass is stored); W is
+ * summed in FP64 in a fixed order, so results are reproducible run to run.
+ * W_dev: dense [n_e][n_m] FP64 table (ising_hist_shape of the plan); dJ_dev:
+ * [n_bonds] FP64 (overwritten); workspace: device memory of at least
+ * ising_bond_workspace bytes, used only during the call's stream order.  All
+ * are device pointers. */
+ising_status ising_bond_backward(const ising_plan *plan, const double *W_dev, double *dJ_dev,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batches: many lattices of uneven size in one persistent launch.          */
 /* ------------------------------------------------------------------------ */
 

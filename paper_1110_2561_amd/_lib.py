@@ -61,6 +61,11 @@ ising_enumerate = _sig("ising_enumerate", i32, vp, vp, vp)
 ising_enumerate_range = _sig("ising_enumerate_range", i32, vp, u64, u64, vp, vp)
 ising_logz = _sig("ising_logz", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp)
 ising_moments = _sig("ising_moments", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp)
+ising_logz_derivatives = _sig("ising_logz_derivatives", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp, vp,
+                              vp, vp, vp, vp)
+ising_bin_weights = _sig("ising_bin_weights", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp)
+ising_bond_workspace = _sig("ising_bond_workspace", i32, vp, ctypes.POINTER(ctypes.c_size_t))
+ising_bond_backward = _sig("ising_bond_backward", i32, vp, vp, vp, vp, ctypes.c_size_t, vp)
 i64p = ctypes.POINTER(ctypes.c_int64)
 ising_batch_plan_create = _sig("ising_batch_plan_create", i32, ctypes.POINTER(ising_lattice), i32,
                                ctypes.POINTER(ising_tune), ctypes.POINTER(vp))

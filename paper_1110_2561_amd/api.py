@@ -15,6 +15,7 @@ from . import _lib
 from .lattice import Lattice
 
 __all__ = ["Plan", "Tune", "enumerate_g", "enumerate_range", "log_z", "moments", "IsingError",
+           "logz_derivatives", "bin_weights", "bond_backward",
            "BatchPlan", "batch_enumerate", "batch_moments", "BatchGraph"]
 
 IsingError = _lib.IsingError
@@ -75,6 +76,14 @@ class Plan:
 
     def new_table(self, device="cuda") -> torch.Tensor:
         return torch.empty((self.n_e, self.n_m), dtype=torch.uint64, device=device)
+
+    @property
+    def bond_workspace_bytes(self) -> int:
+        """Device workspace of bond_backward (ising_bond_workspace); raises
+        IsingError when the per-bond backward does not support this lattice."""
+        n = ctypes.c_size_t()
+        _lib.check(_lib.ising_bond_workspace(self._h, ctypes.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None):
@@ -138,6 +147,49 @@ def moments(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dic
                                   outs["mean_M"].data_ptr(), outs["heat_capacity"].data_ptr(),
                                   outs["susceptibility"].data_ptr(), _stream_handle(stream)))
     return outs
+
+
+def logz_derivatives(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dict:
+    """log Z and its first and second derivatives in (T, h), each [len(T), len(h)]
+    (ising_logz_derivatives): keys log_z, d_T, d_h, d_TT, d_Th, d_hh."""
+    Tt, ht = _grid(T, g.device), _grid(h, g.device)
+    shape = (Tt.numel(), ht.numel())
+    keys = ("log_z", "d_T", "d_h", "d_TT", "d_Th", "d_hh")
+    outs = {k: torch.empty(shape, dtype=torch.float64, device=g.device) for k in keys}
+    n_e, n_m = g.shape
+    _lib.check(_lib.ising_logz_derivatives(g.data_ptr(), n_e, n_m, int(e_min), int(n_spins), Tt.data_ptr(),
+                                           Tt.numel(), ht.data_ptr(), ht.numel(),
+                                           *[outs[k].data_ptr() for k in keys], _stream_handle(stream)))
+    return outs
+
+
+def bin_weights(g: torch.Tensor, e_min: int, n_spins: int, T, h, logz: torch.Tensor, grad: torch.Tensor,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Per-configuration weights W[n_e, n_m] of the loss sum(grad * log Z) (ising_bin_weights)."""
+    Tt, ht = _grid(T, g.device), _grid(h, g.device)
+    shape = (Tt.numel(), ht.numel())
+    lz = logz.to(dtype=torch.float64).contiguous()
+    gr = grad.to(device=g.device, dtype=torch.float64).contiguous()
+    if tuple(lz.shape) != shape or tuple(gr.shape) != shape:
+        raise ValueError(f"logz and grad must have shape {shape}")
+    W = torch.empty(tuple(g.shape), dtype=torch.float64, device=g.device) if out is None else out
+    n_e, n_m = g.shape
+    _lib.check(_lib.ising_bin_weights(g.data_ptr(), n_e, n_m, int(e_min), int(n_spins), Tt.data_ptr(), Tt.numel(),
+                                      ht.data_ptr(), ht.numel(), lz.data_ptr(), gr.data_ptr(), W.data_ptr(),
+                                      _stream_handle(stream)))
+    return W
+
+
+def bond_backward(plan: Plan, W: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """dJ[b] = sum over all configurations of W(E, M) s_i s_j per input bond (ising_bond_backward)."""
+    if not (W.is_cuda and W.dtype == torch.float64 and W.is_contiguous() and tuple(W.shape) == (plan.n_e, plan.n_m)):
+        raise ValueError(f"W must be a contiguous CUDA float64 tensor of shape {(plan.n_e, plan.n_m)}")
+    nb = plan.lattice.n_bonds
+    dJ = torch.empty(nb, dtype=torch.float64, device=W.device) if out is None else out
+    ws = torch.empty(max(plan.bond_workspace_bytes, 8), dtype=torch.uint8, device=W.device)
+    _lib.check(_lib.ising_bond_backward(plan.handle, W.data_ptr(), dJ.data_ptr(), ws.data_ptr(), ws.numel(),
+                                        _stream_handle(stream)))
+    return dJ
 
 
 # ---------------------------------------------------------------------------

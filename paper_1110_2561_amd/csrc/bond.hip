@@ -1,0 +1,360 @@
+// Per-bond backward of log Z: dJ_b = sum over all 2^N configurations of
+// W(E, M) s_i s_j, for a per-bin weight table W (k_bin_weights in
+// thermo.hip makes W from a loss gradient).  Eq. (1) of Peretyatko et al.
+// (Section 2) makes H depend on J_b only through -J_b s_i s_j, so
+// d log Z / dJ_b = <s_i s_j> / T needs, besides g(E, M), the bond spin
+// product of every configuration; the enumeration is recomputed here in the
+// same Gray order as the forward walk, with FP64 sums in place of counts.
+//
+// Per lane and chunk (prefix fixed; k = tile + mj inner bits, mj <= 4):
+//   * the tile walk (2^TJ configurations, only tile bits flip, fully
+//     unrolled) reads W of each configuration from an LDS copy of the table
+//     (one ds_read_b64 on the same running address as the forward's
+//     histogram add) and keeps its running sum sw.  The sum of W over the
+//     configurations with tile spin i up is collected by a prefix-sum trick:
+//     when spin i goes up remember sw, when it goes down add sw minus the
+//     remembered value.  Which spin flips, and which way, is a compile-time
+//     fact of the unrolled Gray sequence, so a step costs one load, one add
+//     and one add or copy.
+//   * per tile block (walk) q the sums S_q = sum W and Y_q,i = sum W s_i are
+//     folded into chunk totals: sum W, sum W s_t, sum W s_m, sum W s_t s_m,
+//     sum W s_m1 s_m2 (s_m, the middle spins, are fixed within a block).
+//   * at the chunk's end every coupled pair takes its sum from one of these
+//     (tile-middle, middle-middle), from sum W s_a times the sign of a prefix
+//     spin b (inner-prefix pairs), or from sum W times s_a s_b (both in the
+//     prefix).  Each pair's value is summed over the wave and added to a
+//     per-wave LDS accumulator; blocks write per-pair partial sums and a
+//     second kernel adds them in block order and scatters them to the input
+//     bonds.  Every sum runs in a fixed order, so results are reproducible.
+// The tile is an independent set of the coupling graph, so there are no
+// tile-tile pairs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "walk.h"
+
+namespace ising {
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(ISING_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxBwBlocks = 1024;
+
+__device__ __forceinline__ double lds_f64(const char *base, uint32_t byte_addr) {
+  return *reinterpret_cast<const double *>(base + byte_addr);
+}
+
+// One tile block of 2^TJ configurations: sw = sum of W, U[i] = sum of W over
+// the configurations with tile spin i up.  Odd blocks start with the top tile
+// bit set (reflected Gray code), so the tile state at step t is
+// gray(t) ^ (ODD ? top : 0).
+template <int TJ, bool ODD>
+__device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ], const char *wt, double &sw,
+                                            double (&U)[TJ]) {
+  constexpr uint32_t kTop = 1u << (TJ - 1);
+  constexpr uint32_t kLast = (1u << TJ) - 1u;
+  constexpr uint32_t kEnd = (kLast ^ (kLast >> 1)) ^ (ODD ? kTop : 0u);
+  double L[TJ];   // running sum before the configuration where spin i last went up
+#pragma unroll
+  for (int i = 0; i < TJ; ++i) {
+    U[i] = 0.0;
+    L[i] = 0.0;
+  }
+  sw = lds_f64(wt, A);
+#pragma unroll
+  for (int t = 1; t < (1 << TJ); ++t) {
+    const int b = __builtin_ctz(t);
+    const uint32_t state = uint32_t(t ^ (t >> 1)) ^ (ODD ? kTop : 0u);
+    const bool up = ((state >> b) & 1u) != 0;
+    A = up ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
+    if (up)
+      L[b] = sw;
+    else
+      U[b] += sw - L[b];
+    sw += lds_f64(wt, A);
+  }
+#pragma unroll
+  for (int i = 0; i < TJ; ++i)
+    if ((kEnd >> i) & 1u) U[i] += sw - L[i];
+}
+
+// Chunk totals of one lane (sums over the chunk's 2^k configurations).
+template <int TJ>
+struct ChunkSums {
+  double S;                 // W
+  double Yt[TJ];            // W s_t, tile spins
+  double Ym[kBwMid];        // W s_m, middle spins
+  double Q[kBwMid][TJ];     // W s_m s_t
+  double M2[6];             // W s_m1 s_m2, pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+
+  __device__ __forceinline__ void clear() {
+    S = 0.0;
+#pragma unroll
+    for (int i = 0; i < TJ; ++i) Yt[i] = 0.0;
+#pragma unroll
+    for (int m = 0; m < kBwMid; ++m) {
+      Ym[m] = 0.0;
+#pragma unroll
+      for (int i = 0; i < TJ; ++i) Q[m][i] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) M2[j] = 0.0;
+  }
+};
+
+template <int TJ, int NC>
+__device__ inline void bond_chunk(const SiteTable<NC> &st, uint64_t x0, uint32_t rep_bytes, const char *wt,
+                                  ChunkSums<TJ> &cs) {
+  uint32_t A;
+  int32_t D[TJ];
+  chunk_start<TJ, NC>(st, x0, rep_bytes, A, D);
+  const uint32_t nblk = 1u << (st.k - TJ);
+  for (uint32_t q = 0; q < nblk; ++q) {
+    double sw, U[TJ];
+    if (q & 1)
+      weight_walk<TJ, true>(A, D, wt, sw, U);
+    else
+      weight_walk<TJ, false>(A, D, wt, sw, U);
+    // middle spins during block q: bits of gray(q) (unused slots read -1 and
+    // are never consulted)
+    const uint32_t mid = q ^ (q >> 1);
+    double sg[kBwMid];
+#pragma unroll
+    for (int m = 0; m < kBwMid; ++m) sg[m] = ((mid >> m) & 1u) ? 1.0 : -1.0;
+    cs.S += sw;
+#pragma unroll
+    for (int i = 0; i < TJ; ++i) {
+      const double y = 2.0 * U[i] - sw;
+      cs.Yt[i] += y;
+#pragma unroll
+      for (int m = 0; m < kBwMid; ++m) cs.Q[m][i] = fma(sg[m], y, cs.Q[m][i]);
+    }
+#pragma unroll
+    for (int m = 0; m < kBwMid; ++m) cs.Ym[m] = fma(sg[m], sw, cs.Ym[m]);
+    int j = 0;
+#pragma unroll
+    for (int m1 = 0; m1 < kBwMid; ++m1)
+#pragma unroll
+      for (int m2 = m1 + 1; m2 < kBwMid; ++m2, ++j) cs.M2[j] = fma(sg[m1] * sg[m2], sw, cs.M2[j]);
+    if (q + 1 < nblk) middle_flip<TJ, NC>(st, x0, q, A, D);
+  }
+}
+
+// Wave total, taken from lane 0 (whose addition order is fixed).
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Add every pair's chunk sum, summed over the wave, to the wave's accumulator.
+template <int TJ>
+__device__ inline void flush_pairs(const BondTables *__restrict__ T, const ChunkSums<TJ> &cs, uint64_t x0,
+                                   double *acc, bool lane0) {
+#pragma unroll
+  for (int m = 0; m < kBwMid; ++m)
+#pragma unroll
+    for (int i = 0; i < TJ; ++i) {
+      const int p = T->qpair[m][i];
+      if (p >= 0) {
+        const double v = wave_total(cs.Q[m][i]);
+        if (lane0) acc[p] += v;
+      }
+    }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int p = T->m2pair[j];
+    if (p >= 0) {
+      const double v = wave_total(cs.M2[j]);
+      if (lane0) acc[p] += v;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < TJ + kBwMid; ++a) {
+    const double V = a < TJ ? cs.Yt[a < TJ ? a : 0] : cs.Ym[a < TJ ? 0 : a - TJ];
+    const int e1 = T->ip_start[a + 1];
+    for (int e = T->ip_start[a]; e < e1; ++e) {
+      const double v = wave_total(((x0 >> T->ip_bit[e]) & 1u) ? V : -V);
+      if (lane0) acc[T->ip_pair[e]] += v;
+    }
+  }
+  const int n_pp = T->n_pp;
+  for (int e = 0; e < n_pp; ++e) {
+    const bool differ = (((x0 >> T->pp_a[e]) ^ (x0 >> T->pp_b[e])) & 1u) != 0;
+    const double v = wave_total(differ ? -cs.S : cs.S);
+    if (lane0) acc[T->pp_pair[e]] += v;
+  }
+}
+
+template <int TJ, int NC>
+__global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
+    const DevPlan *__restrict__ P, const BondTables *__restrict__ T, const double *__restrict__ Wd,
+    uint64_t n_chunks, uint64_t n_tasks, double *__restrict__ partial) {
+  // Static LDS (compile-time base): the weight table at offset 0, then the
+  // per-wave pair accumulators.
+  __shared__ __align__(16) double lds[kHistBytes / 8];
+  const char *wt = reinterpret_cast<const char *>(lds);
+  const int rw = T->rw, Wc = P->W, n_m = P->n_m;
+  const int words = P->n_ec * Wc * rw;
+  for (int w = threadIdx.x; w < words; w += blockDim.x) {
+    const int bin = w / rw;
+    const int e_idx = bin / Wc, nu = bin - e_idx * Wc;
+    const int E = P->e_base + e_idx * P->estep;
+    lds[w] = nu < n_m ? Wd[size_t(E - P->e_min) * n_m + nu] : 0.0;
+  }
+  const int n_pairs = T->n_pairs;
+  double *acc_all = lds + T->wt_bytes / 8;
+  for (int i = threadIdx.x; i < kBwWaves * n_pairs; i += blockDim.x) acc_all[i] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  double *acc = acc_all + wave * n_pairs;
+  SiteTable<NC> st;
+  st.load(P, lane);
+  const uint32_t rep_bytes = uint32_t(lane & (rw - 1)) * 8u;
+  ChunkSums<TJ> cs;
+  for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
+    const uint64_t chunk = t * blockDim.x + threadIdx.x;
+    const uint64_t x0 = chunk << st.k;
+    cs.clear();
+    if (chunk < n_chunks) bond_chunk<TJ, NC>(st, x0, rep_bytes, wt, cs);
+    flush_pairs<TJ>(T, cs, x0, acc, lane == 0);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < kBwWaves; ++w) s += acc_all[w * n_pairs + p];
+    partial[size_t(blockIdx.x) * n_pairs + p] = s;
+  }
+}
+
+// dJ[b] = sum over blocks (in order) of the partial sums of b's pair.
+__global__ void k_bond_finish(const BondTables *__restrict__ T, const int32_t *__restrict__ pair_of_bond,
+                              const double *__restrict__ partial, int blocks, double *__restrict__ dJ) {
+  const int n_pairs = T->n_pairs, n_bonds = T->n_bonds;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_bonds; b += gridDim.x * blockDim.x) {
+    const int p = pair_of_bond[b];
+    double s = 0.0;
+    for (int k = 0; k < blocks; ++k) s += partial[size_t(k) * n_pairs + p];
+    dJ[b] = s;
+  }
+}
+
+// {DevPlan, BondTables, pair_of_bond} of the backward on `device` (lazy).
+static void *bond_device_tables(ising_plan *p, int device, ising_status *st) {
+  *st = ISING_OK;
+  if (device < 0 || device >= kMaxDevices) {
+    *st = fail(ISING_EUNSUPPORTED, "device index out of range");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (!p->bw_copy[device]) {
+    const size_t bytes = sizeof(DevPlan) + sizeof(BondTables) + p->pair_of_bond.size() * sizeof(int32_t);
+    std::vector<char> host(bytes);
+    std::memcpy(host.data(), &p->bw, sizeof(DevPlan));
+    std::memcpy(host.data() + sizeof(DevPlan), &p->bt, sizeof(BondTables));
+    if (!p->pair_of_bond.empty())
+      std::memcpy(host.data() + sizeof(DevPlan) + sizeof(BondTables), p->pair_of_bond.data(),
+                  p->pair_of_bond.size() * sizeof(int32_t));
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+      *st = fail(ISING_EHIP, std::string("hipMalloc(backward tables): ") + hipGetErrorString(e));
+      return nullptr;
+    }
+    e = hipMemcpy(ptr, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(ptr);
+      *st = fail(ISING_EHIP, std::string("hipMemcpy(backward tables): ") + hipGetErrorString(e));
+      return nullptr;
+    }
+    p->bw_copy[device] = ptr;
+  }
+  return p->bw_copy[device];
+}
+
+template <int TJ, int NC>
+static ising_status launch_bond(const DevPlan *dP, const BondTables *dT, const double *W, uint64_t n_chunks,
+                                uint64_t n_tasks, int grid, double *partial, hipStream_t s) {
+  hipLaunchKernelGGL((k_bond_backward<TJ, NC>), dim3(grid), dim3(kBwWaves * kWave), 0, s, dP, dT, W, n_chunks,
+                     n_tasks, partial);
+  HIP_TRY(hipGetLastError());
+  return ISING_OK;
+}
+
+static ising_status bond_dispatch(int tile, int n_classes, const DevPlan *dP, const BondTables *dT, const double *W,
+                                  uint64_t n_chunks, uint64_t n_tasks, int grid, double *partial, hipStream_t s) {
+#define ISING_BW_NC(TJ)                                                                       \
+  switch (n_classes) {                                                                        \
+    case 1: return launch_bond<TJ, 1>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
+    case 2: return launch_bond<TJ, 2>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
+    case 4: return launch_bond<TJ, 4>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
+    case 8: return launch_bond<TJ, 8>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
+  }                                                                                           \
+  break;
+  switch (tile) {
+    case 1: ISING_BW_NC(1)
+    case 2: ISING_BW_NC(2)
+    case 3: ISING_BW_NC(3)
+    case 4: ISING_BW_NC(4)
+    case 5: ISING_BW_NC(5)
+    case 6: ISING_BW_NC(6)
+    case 7: ISING_BW_NC(7)
+    case 8: ISING_BW_NC(8)
+  }
+#undef ISING_BW_NC
+  return fail(ISING_EUNSUPPORTED, "tile bits or class count out of range");
+}
+
+}  // namespace ising
+
+using namespace ising;
+
+extern "C" ising_status ising_bond_workspace(const ising_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(ISING_EINVAL, "plan or bytes is NULL");
+  if (p->bw_status != ISING_OK) return fail(p->bw_status, p->bw_error);
+  *bytes = size_t(kMaxBwBlocks) * size_t(std::max(p->bt.n_pairs, 1)) * sizeof(double);
+  return ISING_OK;
+}
+
+extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev,
+                                            void *workspace, size_t workspace_bytes, void *stream) {
+  if (!pc) return fail(ISING_EINVAL, "plan is NULL");
+  if (pc->bw_status != ISING_OK) return fail(pc->bw_status, pc->bw_error);
+  if (pc->n_bonds == 0) return ISING_OK;
+  if (!W_dev || !dJ_dev || !workspace) return fail(ISING_EINVAL, "W_dev, dJ_dev or workspace is NULL");
+  size_t need = 0;
+  ising_status st = ising_bond_workspace(pc, &need);
+  if (st != ISING_OK) return st;
+  if (workspace_bytes < need)
+    return fail(ISING_EINVAL, "workspace of " + std::to_string(workspace_bytes) + " bytes; " +
+                                  std::to_string(need) + " needed");
+  ising_plan *p = const_cast<ising_plan *>(pc);  // only the lazy device copy is written
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  char *tables = static_cast<char *>(bond_device_tables(p, dev, &st));
+  if (!tables) return st;
+  const DevPlan *dP = reinterpret_cast<const DevPlan *>(tables);
+  const BondTables *dT = reinterpret_cast<const BondTables *>(tables + sizeof(DevPlan));
+  const int32_t *dmap = reinterpret_cast<const int32_t *>(tables + sizeof(DevPlan) + sizeof(BondTables));
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const uint64_t n_chunks = uint64_t(1) << (p->bw.n - p->bw.inner);
+  const uint64_t block = uint64_t(kBwWaves) * kWave;
+  const uint64_t n_tasks = (n_chunks + block - 1) / block;
+  const int grid = int(std::min<uint64_t>({n_tasks, uint64_t(cus), uint64_t(kMaxBwBlocks)}));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *partial = static_cast<double *>(workspace);
+  st = bond_dispatch(p->bw.tile, p->bw.n_classes, dP, dT, W_dev, n_chunks, n_tasks, grid, partial, s);
+  if (st != ISING_OK) return st;
+  const int fb = std::min((p->n_bonds + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(fb)), dim3(256), 0, s, dT, dmap, partial, grid, dJ_dev);
+  HIP_TRY(hipGetLastError());
+  return ISING_OK;
+}

@@ -182,8 +182,10 @@ using namespace ising;
 
 extern "C" ising_status ising_plan_destroy(ising_plan *p) {
   if (!p) return ISING_OK;
-  for (int d = 0; d < kMaxDevices; ++d)
+  for (int d = 0; d < kMaxDevices; ++d) {
     if (p->dev_copy[d]) (void)hipFree(p->dev_copy[d]);
+    if (p->bw_copy[d]) (void)hipFree(p->bw_copy[d]);
+  }
   delete p;
   return ISING_OK;
 }

@@ -91,6 +91,111 @@ static void place_lane_spins(int n, int k, int R, const std::vector<int64_t> &J,
   while (ie < even_sites.size()) *dst++ = even_sites[ie++];
 }
 
+// Geometry and pair tables of the per-bond backward walk (see bond.hip).  It
+// keeps the forward bit order: tile bits [0, TJ), then mj <= 4 middle bits,
+// the rest prefix.  Pairs are the distinct (i, j) of the input bonds, also
+// those whose couplings cancel (their spin products still have averages).  Byte constants address an FP64 weight table with rw
+// interleaved copies: word (bin * rw + copy), bin = e_idx * W + n_up.
+static void plan_backward(ising_plan *p, const ising_lattice *lat, const std::vector<int64_t> &J,
+                          const std::vector<int64_t> &classes) {
+  const DevPlan &d = p->dev;
+  const int n = d.n, TJ = d.tile;
+  const int mj = std::min(kBwMid, n - TJ);
+  const int kb = TJ + mj;
+  auto bad = [&](const std::string &m) {
+    p->bw_status = ISING_EUNSUPPORTED;
+    p->bw_error = m;
+  };
+  // distinct pairs in order of first appearance among the input bonds
+  std::vector<int32_t> pid(size_t(n) * n, -1);
+  std::vector<std::pair<int, int>> pairs;
+  p->pair_of_bond.assign(size_t(lat->n_bonds), -1);
+  for (int b = 0; b < lat->n_bonds; ++b) {
+    const int i = std::min(lat->bond_i[b], lat->bond_j[b]), j = std::max(lat->bond_i[b], lat->bond_j[b]);
+    int32_t &slot = pid[size_t(i) * n + j];
+    if (slot < 0) {
+      slot = int32_t(pairs.size());
+      pairs.push_back({i, j});
+    }
+    p->pair_of_bond[b] = slot;
+  }
+  if ((int)pairs.size() > kMaxPairs) {
+    bad(std::to_string(pairs.size()) + " distinct coupled pairs (the backward handles " +
+        std::to_string(kMaxPairs) + ")");
+    return;
+  }
+  const int n_pairs = (int)pairs.size();
+  // weight-table copies that fit next to the per-wave pair accumulators
+  const int64_t acc_bytes = int64_t(kBwWaves) * std::max(n_pairs, 1) * 8;
+  const int64_t copy_bytes = int64_t(d.n_ec) * d.W * 8;
+  int rw = 8;
+  while (rw > 1 && copy_bytes * rw + acc_bytes > kHistBytes) rw >>= 1;
+  if (copy_bytes * rw + acc_bytes > kHistBytes) {
+    bad("FP64 weight table of " + std::to_string(d.n_ec) + " x " + std::to_string(d.W) +
+        " bins does not fit the LDS");
+    return;
+  }
+  DevPlan &w = p->bw;
+  w = d;
+  w.inner = kb;
+  w.R = 2 * rw;   // row bytes W * R * 4 = W * rw * 8
+  const int64_t row_bytes = int64_t(w.W) * w.R * 4, col_bytes = int64_t(w.R) * 4;
+  for (int c = 0; c < (int)classes.size(); ++c)
+    w.cls_step[c] = (int32_t)((4 * classes[c] / w.estep) * row_bytes);
+  for (int b = 0; b < n; ++b) w.up_base[b] = (int32_t)((2 * int64_t(w.hdeg[b]) / w.estep) * row_bytes + col_bytes);
+  std::memset(w.kmid, 0, sizeof(w.kmid));
+  for (int m = TJ; m < kb; ++m)
+    for (int i = 0; i < TJ; ++i) {
+      const int64_t v = J[size_t(p->site_of_bit[m]) * n + p->site_of_bit[i]];
+      w.kmid[m - TJ][i] = (int32_t)((-4 * v / w.estep) * row_bytes);
+    }
+
+  BondTables &t = p->bt;
+  t = BondTables{};
+  t.n_pairs = n_pairs;
+  t.mj = mj;
+  t.rw = rw;
+  t.wt_bytes = (int32_t)(copy_bytes * rw);
+  t.n_bonds = lat->n_bonds;
+  for (auto &row : t.qpair)
+    for (auto &v : row) v = -1;
+  for (auto &v : t.m2pair) v = -1;
+  std::vector<std::vector<std::pair<int, int>>> ip(static_cast<size_t>(kb));   // inner bit -> (pair, prefix bit)
+  for (int q = 0; q < n_pairs; ++q) {
+    int a = p->bit_of_site[pairs[q].first], b = p->bit_of_site[pairs[q].second];
+    if (a > b) std::swap(a, b);
+    if (b < TJ) {   // the tile holds no listed pair
+      bad("internal: bond pair inside the tile");
+      return;
+    }
+    if (b < kb) {
+      if (a < TJ) t.qpair[b - TJ][a] = (int16_t)q;
+      else {
+        const int m1 = a - TJ, m2 = b - TJ;
+        t.m2pair[m1 * (7 - m1) / 2 + (m2 - m1 - 1)] = (int16_t)q;
+      }
+    } else if (a < kb) {
+      ip[size_t(a)].push_back({q, b});
+    } else {
+      t.pp_pair[t.n_pp] = (int16_t)q;
+      t.pp_a[t.n_pp] = (uint8_t)a;
+      t.pp_b[t.n_pp] = (uint8_t)b;
+      ++t.n_pp;
+    }
+  }
+  int e = 0;
+  for (int a = 0; a <= kMaxTile + kBwMid; ++a) {
+    t.ip_start[a] = (int16_t)e;
+    if (a < kb)
+      for (auto &pr : ip[size_t(a)]) {
+        t.ip_pair[e] = (int16_t)pr.first;
+        t.ip_bit[e] = (uint8_t)pr.second;
+        ++e;
+      }
+  }
+  t.n_ip = e;
+}
+
 extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_tune *tune,
                                           ising_plan **out) {
   return ising::plan_create_internal(lat, tune, 1, out);
@@ -119,6 +224,7 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
   const int64_t kJmax = int64_t(1) << 20;
   int64_t S = 0;
   std::vector<int64_t> J(size_t(n) * n, 0);
+  std::vector<char> listed(size_t(n) * n, 0);   // pair appears among the bonds (even if its couplings cancel)
   for (int b = 0; b < lat->n_bonds; ++b) {
     const int i = lat->bond_i[b], j = lat->bond_j[b];
     const int64_t v = lat->bond_J[b];
@@ -130,6 +236,7 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
     if (S > kJmax) return fail(ISING_ERANGE, "sum |J| exceeds 2^20");
     J[size_t(std::min(i, j)) * n + std::max(i, j)] += v;
     J[size_t(std::max(i, j)) * n + std::min(i, j)] += v;
+    listed[size_t(i) * n + j] = listed[size_t(j) * n + i] = 1;
   }
 
   // ---- coupling classes and the compact energy lattice ----
@@ -184,9 +291,10 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
   // array, so histogram addresses need no base add): one block per CU.
   const int bpc = 1;
 
-  // ---- tile: an independent set (no merged coupling between members), by
-  // the minimum-degree greedy rule: take a site of least remaining degree,
-  // drop it and its neighbours, repeat ----
+  // ---- tile: an independent set (no listed pair between members, so no
+  // merged coupling either, and the per-bond backward never sees a pair
+  // inside the tile), by the minimum-degree greedy rule: take a site of least
+  // remaining degree, drop it and its neighbours, repeat ----
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degree[a] > degree[b]; });
@@ -194,7 +302,9 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
   const int tile_want = tn.tile_bits ? tn.tile_bits : kMaxTile;
   {
     std::vector<char> alive(n, 1);
-    std::vector<int> rem(degree);
+    std::vector<int> rem(n, 0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) rem[i] += listed[size_t(i) * n + j];
     while ((int)tile.size() < tile_want) {
       int best = -1;
       for (int s2 = 0; s2 < n; ++s2)
@@ -203,11 +313,11 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
       tile.push_back(best);
       std::vector<int> gone{best};
       for (int j = 0; j < n; ++j)
-        if (alive[j] && j != best && J[size_t(best) * n + j]) gone.push_back(j);
+        if (alive[j] && j != best && listed[size_t(best) * n + j]) gone.push_back(j);
       for (int g2 : gone) {
         alive[g2] = 0;
         for (int j = 0; j < n; ++j)
-          if (alive[j] && J[size_t(g2) * n + j]) --rem[j];
+          if (alive[j] && listed[size_t(g2) * n + j]) --rem[j];
       }
     }
   }
@@ -296,6 +406,7 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
       // tile spin i's up-flip delta, in bytes, changes by this when bit m goes up
       d.kmid[m - TJ][i] = (int32_t)((-4 * v / estep) * row_bytes);
     }
+  plan_backward(p, lat, J, classes);
   *out = p;
   set_error("");
   return ISING_OK;

@@ -105,13 +105,14 @@ __device__ __forceinline__ uint32_t lane_copy(uint32_t lane, int R) {
   return lane & uint32_t(R - 1);
 }
 
-// All 2^k configurations of one chunk (prefix bits fixed).
+// First configuration of a chunk (prefix bits fixed, inner bits zero): its
+// histogram byte address A = e_idx * row + n_up * col + extra, and the
+// up-flip address change D_i of every tile spin (their neighbours are all
+// outside the tile, so these stay fixed while only tile bits flip).
 template <int TJ, int NC>
-__device__ inline void walk_chunk(const SiteTable<NC> &st, uint64_t chunk, uint32_t rep, char *hist) {
-  const int k = st.k;
-  const uint64_t x0 = chunk << k;
+__device__ __forceinline__ void chunk_start(const SiteTable<NC> &st, uint64_t x0, uint32_t extra, uint32_t &A,
+                                            int32_t (&D)[TJ]) {
   const uint32_t x0lo = uint32_t(x0), x0hi = uint32_t(x0 >> 32);
-
   // Full (E, n_up) of the first configuration: E = -(1/2) sum_i s_i h_i.
   int32_t hs = 0;
   for (int i = 0; i < st.n; ++i) {
@@ -120,35 +121,45 @@ __device__ inline void walk_chunk(const SiteTable<NC> &st, uint64_t chunk, uint3
   }
   const int32_t E0 = -(hs / 2);
   const int32_t nup = __popcll(x0);
-  uint32_t A = uint32_t(((E0 - st.e_base) / st.estep) * st.row_bytes + nup * st.col_bytes) + rep * 4u;
-
-  // Up-flip address change of each tile spin (its neighbours are all outside
-  // the tile, so these stay fixed while only tile bits flip).
-  int32_t D[TJ];
+  A = uint32_t(((E0 - st.e_base) / st.estep) * st.row_bytes + nup * st.col_bytes) + extra;
 #pragma unroll
   for (int i = 0; i < TJ; ++i) D[i] = st.up_delta(i, x0lo, x0hi);
+}
 
-  const uint32_t nblk = 1u << (k - TJ);
+// Gray step q -> q+1 of the middle bits (between tile blocks): it flips bit
+// TJ + ctz(q+1); move A by that spin's delta and the D_i of the tile spins
+// coupled to it by the plan constants kmid.
+template <int TJ, int NC>
+__device__ __forceinline__ void middle_flip(const SiteTable<NC> &st, uint64_t x0, uint32_t q, uint32_t &A,
+                                            int32_t (&D)[TJ]) {
+  const uint32_t q1 = q + 1;
+  const int mm = __builtin_ctz(q1);
+  const bool up = (((q1 ^ (q1 >> 1)) >> mm) & 1u) != 0;
+  // current inner bits: tile at its end state, middle bits = gray(q)
+  const uint64_t x = x0 | ((q & 1) ? 0ull : (1ull << (TJ - 1))) | (uint64_t(q ^ (q >> 1)) << TJ);
+  const int32_t dm = st.up_delta(TJ + mm, uint32_t(x), uint32_t(x >> 32));
+  A = up ? A + uint32_t(dm) : A - uint32_t(dm);
+#pragma unroll
+  for (int i = 0; i < TJ; ++i) {
+    const int32_t kv = __builtin_amdgcn_readlane(st.kmid[i], mm);
+    D[i] = up ? D[i] + kv : D[i] - kv;
+  }
+}
+
+// All 2^k configurations of one chunk (prefix bits fixed).
+template <int TJ, int NC>
+__device__ inline void walk_chunk(const SiteTable<NC> &st, uint64_t chunk, uint32_t rep, char *hist) {
+  const uint64_t x0 = chunk << st.k;
+  uint32_t A;
+  int32_t D[TJ];
+  chunk_start<TJ, NC>(st, x0, rep * 4u, A, D);
+  const uint32_t nblk = 1u << (st.k - TJ);
   for (uint32_t q = 0; q < nblk; ++q) {
     if (q & 1)
       tile_walk<TJ, true>(A, D, hist);
     else
       tile_walk<TJ, false>(A, D, hist);
-    if (q + 1 < nblk) {
-      // Gray step q -> q+1 of the middle bits flips bit TJ + ctz(q+1).
-      const uint32_t q1 = q + 1;
-      const int mm = __builtin_ctz(q1);
-      const bool up = (((q1 ^ (q1 >> 1)) >> mm) & 1u) != 0;
-      // current inner bits: tile at its end state, middle bits = gray(q)
-      const uint64_t inner = ((q & 1) ? 0ull : (1ull << (TJ - 1))) | (uint64_t(q ^ (q >> 1)) << TJ);
-      const int32_t dm = st.up_delta(TJ + mm, x0lo | uint32_t(inner), x0hi | uint32_t(inner >> 32));
-      A = up ? A + uint32_t(dm) : A - uint32_t(dm);
-#pragma unroll
-      for (int i = 0; i < TJ; ++i) {
-        const int32_t kv = __builtin_amdgcn_readlane(st.kmid[i], mm);
-        D[i] = up ? D[i] + kv : D[i] - kv;
-      }
-    }
+    if (q + 1 < nblk) middle_flip<TJ, NC>(st, x0, q, A, D);
   }
 }
 

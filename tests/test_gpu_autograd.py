@@ -1,0 +1,257 @@
+"""Derivatives of log Z on the GPU against the oracle: the (T, h) derivative
+kernel, the per-bin weights, the per-bond backward (recomputed enumeration),
+the autograd Function (first derivatives, finite differences, double
+backward for C and chi), and the 6x6 torus against Kaufman's closed form."""
+import zlib
+
+import mpmath as mp
+import numpy as np
+import pytest
+import torch
+
+from oracle import closed_forms, grad, native, thermo
+from paper_1110_2561_amd import lattice as L
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1110_2561_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def ag():
+    from paper_1110_2561_amd import autograd as M
+    return M
+
+
+def _tri(N, Lx, seed):
+    base = L.triangular_free(N, Lx)
+    return L.triangular_free(N, Lx, L.choice_couplings(base.n_bonds, seed))
+
+
+LATS = {
+    "torus4x4": L.square_torus(4, 4),
+    "cubic3_pm": L.cubic_torus(3, L.choice_couplings(81, 6)),
+    "tri19": _tri(19, 5, 11),
+    "random14_4cls": L.random_bond_lattice(14, 40, 7, values=(-2, -1, 1, 2)),
+    "ring9": L.ring(9, L.pm_couplings(9, 3)),
+    "repeated": L.Lattice(6, [0, 1, 1, 2, 4, 0, 5], [1, 2, 2, 3, 5, 5, 3], [1, -2, 3, 1, -1, 2, 2]),
+    "tiny3": L.Lattice(3, [0, 1], [1, 2], [2, -1]),
+    "torus4x5_pm": L.square_torus(4, 5, L.pm_couplings(40, 5)),
+}
+
+_SPLIT = {}
+
+
+def _split(name):
+    if name not in _SPLIT:
+        lat = LATS[name]
+        print(f"oracle bond split {name} N={lat.n_spins}", flush=True)
+        _SPLIT[name] = native.bond_split(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J)
+    return _SPLIT[name]
+
+
+def _dev_table(g):
+    return torch.from_numpy(np.ascontiguousarray(g).view(np.int64)).view(torch.uint64).cuda()
+
+
+T_GRID = np.array([0.6, 1.1, 2.269, 3.7])
+H_GRID = np.array([-0.7, 0.0, 0.35])
+
+
+@pytest.mark.parametrize("name", ["torus4x4", "random14_4cls", "ring9"])
+def test_logz_derivatives_match_oracle(api, name):
+    lat = LATS[name]
+    g, _ = _split(name)
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    out = api.logz_derivatives(_dev_table(g), -S, N, T_GRID, H_GRID)
+    ref = grad.log_z_derivatives(g, -S, N, T_GRID, H_GRID)
+    np.testing.assert_allclose(out["log_z"].cpu().numpy(), thermo.log_z(g, -S, N, T_GRID, H_GRID), rtol=1e-13)
+    for k, v in ref.items():
+        scale = np.abs(v).max() + 1e-300
+        np.testing.assert_allclose(out[k].cpu().numpy(), v, rtol=1e-11, atol=1e-12 * scale, err_msg=k)
+
+
+@pytest.mark.parametrize("name", ["torus4x4", "cubic3_pm", "ring9"])
+def test_bin_weights_match_oracle(api, name):
+    lat = LATS[name]
+    g, _ = _split(name)
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    G = np.random.default_rng(1).standard_normal((T_GRID.size, H_GRID.size))
+    lz = api.log_z(_dev_table(g), -S, N, T_GRID, H_GRID)
+    W = api.bin_weights(_dev_table(g), -S, N, T_GRID, H_GRID, lz, torch.from_numpy(G).cuda()).cpu().numpy()
+    ref = grad.bin_weights(g, -S, N, T_GRID, H_GRID, G)
+    np.testing.assert_allclose(W, ref, rtol=1e-12, atol=1e-15 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", list(LATS))
+def test_bond_backward_matches_oracle(api, name):
+    lat = LATS[name]
+    g, gp = _split(name)
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    # a weight table with structure on every realised bin (and junk on empty ones,
+    # which no configuration reads)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    W = rng.standard_normal(g.shape) * np.exp(-rng.uniform(0, 3, g.shape))
+    plan = api.Plan(lat)
+    print(f"{name}: N={N} tile={plan.tile_bits} bonds={lat.n_bonds}", flush=True)
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    ref = grad.bond_grad_from_weights(g, gp, np.where(g > 0, W, 0.0))
+    scale = (np.abs(W) * g.astype(np.float64)).sum()
+    np.testing.assert_allclose(dJ, ref, rtol=0, atol=1e-13 * scale)
+
+
+def test_bond_backward_is_reproducible_and_matches_small_tune(api):
+    lat = LATS["cubic3_pm"]
+    g, gp = _split("cubic3_pm")
+    W = np.random.default_rng(5).uniform(-1, 1, g.shape)
+    Wd = torch.from_numpy(W).cuda()
+    a = api.bond_backward(api.Plan(lat), Wd)
+    b = api.bond_backward(api.Plan(lat), Wd)
+    assert torch.equal(a, b)                                   # fixed summation order
+    c = api.bond_backward(api.Plan(lat, api.Tune(tile_bits=3)), Wd)   # another tile and walk
+    np.testing.assert_allclose(c.cpu().numpy(), a.cpu().numpy(), rtol=1e-12, atol=1e-12 * np.abs(W).max() * 2 ** 27)
+
+
+def test_bond_backward_edge_cases(api):
+    # no bonds: nothing to do
+    p0 = api.Plan(L.Lattice(5, [], [], []))
+    assert api.bond_backward(p0, torch.zeros((1, 6), dtype=torch.float64, device="cuda")).numel() == 0
+    # couplings of one pair that cancel: its spin product still has an average
+    lat = L.Lattice(4, [0, 0, 1, 2], [1, 1, 2, 3], [1, -1, 2, -1])
+    g, gp = native.bond_split(4, lat.bond_i, lat.bond_j, lat.bond_J)
+    W = np.random.default_rng(8).uniform(0.5, 1.5, g.shape)
+    dJ = api.bond_backward(api.Plan(lat), torch.from_numpy(W).cuda()).cpu().numpy()
+    np.testing.assert_allclose(dJ, grad.bond_grad_from_weights(g, gp, np.where(g > 0, W, 0.0)), rtol=1e-14)
+    assert dJ[0] == dJ[1] and dJ[0] != 0.0
+    # N = 1 with no bonds, N = 2 with one bond
+    lat = L.Lattice(2, [0], [1], [3])
+    g, gp = native.bond_split(2, lat.bond_i, lat.bond_j, lat.bond_J)
+    W = np.arange(g.size, dtype=np.float64).reshape(g.shape)
+    dJ = api.bond_backward(api.Plan(lat), torch.from_numpy(W).cuda()).cpu().numpy()
+    np.testing.assert_allclose(dJ, grad.bond_grad_from_weights(g, gp, np.where(g > 0, W, 0.0)), rtol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# autograd
+# --------------------------------------------------------------------------
+
+def test_autograd_first_derivatives_match_oracle(ag):
+    name = "cubic3_pm"
+    lat = LATS[name]
+    g, gp = _split(name)
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    f = ag.IsingLogZ(lat)
+    T = torch.tensor(T_GRID, device="cuda", requires_grad=True)
+    h = torch.tensor(H_GRID, device="cuda", requires_grad=True)
+    J = f.couplings()
+    lz = f(T, h, J)
+    np.testing.assert_allclose(lz.detach().cpu().numpy(), thermo.log_z(g, -S, N, T_GRID, H_GRID), rtol=1e-13)
+    G = np.random.default_rng(3).standard_normal(lz.shape)
+    gT, gh, gJ = torch.autograd.grad((lz * torch.from_numpy(G).cuda()).sum(), (T, h, J))
+    d = grad.log_z_derivatives(g, -S, N, T_GRID, H_GRID)
+    np.testing.assert_allclose(gT.cpu().numpy(), (G * d["d_T"]).sum(1), rtol=1e-11)
+    np.testing.assert_allclose(gh.cpu().numpy(), (G * d["d_h"]).sum(0), rtol=1e-11, atol=1e-12)
+    refJ = (G[None] * grad.bond_grad(g, gp, -S, N, T_GRID, H_GRID)).sum(axis=(1, 2))
+    np.testing.assert_allclose(gJ.cpu().numpy(), refJ, rtol=1e-10, atol=1e-12 * np.abs(refJ).max())
+
+
+def test_autograd_matches_central_finite_differences(ag):
+    name = "tri19"
+    lat = LATS[name]
+    g, gp = _split(name)
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    f = ag.IsingLogZ(lat)
+    T0, h0, d = 1.7, 0.3, 1e-5
+    T = torch.tensor([T0], device="cuda", dtype=torch.float64, requires_grad=True)
+    h = torch.tensor([h0], device="cuda", dtype=torch.float64, requires_grad=True)
+    J = f.couplings()
+    gT, gh, gJ = torch.autograd.grad(f(T, h, J).sum(), (T, h, J))
+    lz = lambda t, hh: float(f(torch.tensor([t], device="cuda", dtype=torch.float64),   # noqa: E731
+                               torch.tensor([hh], device="cuda", dtype=torch.float64))[0, 0])
+    assert gT.item() == pytest.approx((lz(T0 + d, h0) - lz(T0 - d, h0)) / (2 * d), rel=1e-7)
+    assert gh.item() == pytest.approx((lz(T0, h0 + d) - lz(T0, h0 - d)) / (2 * d), rel=1e-7)
+    # couplings: J_b +- 1e-5 is not an integer, so the oracle's bond split evaluates it
+    for b in range(0, lat.n_bonds, 7):
+        fd = (grad.log_z_shifted(g, gp[b], -S, N, T0, h0, d) - grad.log_z_shifted(g, gp[b], -S, N, T0, h0, -d)) / (2 * d)
+        assert gJ[b].item() == pytest.approx(fd, rel=1e-6, abs=1e-9), b
+
+
+def test_double_backward_gives_heat_capacity_and_susceptibility(api, ag):
+    name = "random14_4cls"
+    lat = LATS[name]
+    g, _ = _split(name)
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    f = ag.IsingLogZ(lat)
+    for h0 in (0.0, 0.45):
+        T = torch.tensor(T_GRID, device="cuda", requires_grad=True)
+        h = torch.tensor([h0], device="cuda", dtype=torch.float64, requires_grad=True)
+        lz = f(T, h)
+        dT, dh = torch.autograd.grad(lz.sum(), (T, h), create_graph=True)
+        H = T * T * dT                         # <E - hM> per temperature
+        C = torch.autograd.grad(H.sum(), T, retain_graph=True)[0]
+        mE, mM, Cref, chiref = thermo.moments(g, -S, N, T_GRID, [h0])
+        np.testing.assert_allclose(H.detach().cpu().numpy(), (mE - h0 * mM)[:, 0], rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(C.cpu().numpy(), Cref[:, 0], rtol=1e-10)
+        # chi at each T separately (h has one point): <M> = T d log Z/dh
+        for a, t in enumerate(T_GRID):
+            Ta = torch.tensor([t], device="cuda", dtype=torch.float64)
+            ha = torch.tensor([h0], device="cuda", dtype=torch.float64, requires_grad=True)
+            (dha,) = torch.autograd.grad(f(Ta, ha).sum(), ha, create_graph=True)
+            chi = torch.autograd.grad((t * dha).sum(), ha)[0]
+            assert chi.item() == pytest.approx(chiref[a, 0], rel=1e-10)
+        mom = api.moments(_dev_table(g), -S, N, T_GRID, [h0])
+        np.testing.assert_allclose(C.cpu().numpy(), mom["heat_capacity"][:, 0].cpu().numpy(), rtol=1e-10)
+
+
+def test_second_derivative_in_couplings_raises(ag):
+    f = ag.IsingLogZ(LATS["torus4x4"])
+    J = f.couplings()
+    T = torch.tensor([2.0], device="cuda", dtype=torch.float64)
+    (gJ,) = torch.autograd.grad(f(T, torch.tensor([0.0], device="cuda", dtype=torch.float64), J).sum(), J,
+                                create_graph=True)
+    with pytest.raises(RuntimeError, match="not implemented"):
+        torch.autograd.grad(gJ.sum(), J)
+
+
+def test_couplings_must_match_lattice(ag):
+    f = ag.IsingLogZ(LATS["torus4x4"])
+    J = f.couplings().detach().clone()
+    J[0] = 0.5
+    with pytest.raises(ValueError, match="integer couplings"):
+        f(torch.tensor([1.0], device="cuda", dtype=torch.float64), torch.tensor([0.0], device="cuda",
+                                                                                dtype=torch.float64), J)
+
+
+# --------------------------------------------------------------------------
+# 6x6 torus (2^36 configurations): per-bond gradients against Kaufman
+# --------------------------------------------------------------------------
+
+def test_torus6x6_bond_gradients_match_kaufman_and_sum_rule(api, ag):
+    lat = L.square_torus(6, 6)
+    f = ag.IsingLogZ(lat)
+    T_list = np.array([1.5, 2.269, 3.0])
+    h_list = np.array([0.0, 0.2])
+    T = torch.tensor(T_list, device="cuda")
+    h = torch.tensor(h_list, device="cuda")
+    J = f.couplings()
+    gref = native.tm_torus(*L.torus_coupling_grids(lat))
+    for a, t in enumerate(T_list):
+        for c, hh in enumerate(h_list):
+            sel = torch.zeros((T_list.size, h_list.size), dtype=torch.float64, device="cuda")
+            sel[a, c] = 1.0
+            (gJ,) = torch.autograd.grad((f(T, h, J) * sel).sum(), J)
+            gJ = gJ.cpu().numpy()
+            # edge-transitive torus at uniform J: every bond has the same gradient
+            np.testing.assert_allclose(gJ, gJ.mean(), rtol=1e-11)
+            # sum rule: sum_b J_b d log Z/dJ_b = -<E>/T, with <E> from the oracle's exact table
+            mE, _, _, _ = thermo.moments(gref, -72, 36, [t], [hh])
+            assert float((lat.bond_J * gJ).sum()) == pytest.approx(-mE[0, 0] / t, rel=1e-11)
+            if hh == 0.0:
+                with mp.workdps(40):
+                    dK = float(mp.diff(lambda Jv: closed_forms.kaufman_logz(6, 6, t / Jv), 1))
+                np.testing.assert_allclose(gJ, dK / lat.n_bonds, rtol=1e-10)
