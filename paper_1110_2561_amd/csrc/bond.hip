@@ -22,8 +22,8 @@
 //   * at the chunk's end every coupled pair takes its sum from one of these
 //     (tile-middle, middle-middle), from sum W s_a times the sign of a prefix
 //     spin b (inner-prefix pairs), or from sum W times s_a s_b (both in the
-//     prefix).  Each pair's value is summed over the wave and added to a
-//     per-wave LDS accumulator; blocks write per-pair partial sums and a
+//     prefix).  Each pair's value is summed over the wave (a DPP tree) and
+//     added to a per-wave LDS accumulator; blocks write per-pair partial sums and a
 //     second kernel adds them in block order and scatters them to the input
 //     bonds.  Every sum runs in a fixed order, so results are reproducible.
 // The tile is an independent set of the coupling graph, so there are no
@@ -56,29 +56,55 @@ __device__ __forceinline__ double lds_f64(const char *base, uint32_t byte_addr) 
 // bit set (reflected Gray code), so the tile state at step t is
 // gray(t) ^ (ODD ? top : 0).
 template <int TJ, bool ODD>
+__host__ __device__ constexpr uint32_t tile_state(int t) {
+  return uint32_t(t ^ (t >> 1)) ^ (ODD ? (1u << (TJ - 1)) : 0u);
+}
+
+template <int TJ, bool ODD>
 __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ], const char *wt, double &sw,
                                             double (&U)[TJ]) {
-  constexpr uint32_t kTop = 1u << (TJ - 1);
-  constexpr uint32_t kLast = (1u << TJ) - 1u;
-  constexpr uint32_t kEnd = (kLast ^ (kLast >> 1)) ^ (ODD ? kTop : 0u);
+  constexpr int kN = 1 << TJ;
+  constexpr int kG = kN < 8 ? kN : 8;   // configurations per load group
+  constexpr int kGroups = kN / kG;
+  constexpr uint32_t kEnd = tile_state<TJ, ODD>(kN - 1);
   double L[TJ];   // running sum before the configuration where spin i last went up
 #pragma unroll
   for (int i = 0; i < TJ; ++i) {
     U[i] = 0.0;
     L[i] = 0.0;
   }
-  sw = lds_f64(wt, A);
+  sw = 0.0;
+  // W of configuration t is loaded one group ahead of its use, so the LDS
+  // latency of a group overlaps the sums of the previous one.
+  double w[2][kG];
 #pragma unroll
-  for (int t = 1; t < (1 << TJ); ++t) {
-    const int b = __builtin_ctz(t);
-    const uint32_t state = uint32_t(t ^ (t >> 1)) ^ (ODD ? kTop : 0u);
-    const bool up = ((state >> b) & 1u) != 0;
-    A = up ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
-    if (up)
-      L[b] = sw;
-    else
-      U[b] += sw - L[b];
-    sw += lds_f64(wt, A);
+  for (int g = 0; g <= kGroups; ++g) {
+    if (g < kGroups) {
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int t = g * kG + u;
+        if (t > 0) {
+          const int b = __builtin_ctz(t);
+          A = ((tile_state<TJ, ODD>(t) >> b) & 1u) ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
+        }
+        w[g & 1][u] = lds_f64(wt, A);
+      }
+    }
+    if (g > 0) {
+      const int gp = g - 1;
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int t = gp * kG + u;
+        if (t > 0) {   // spin b flipped on entering configuration t
+          const int b = __builtin_ctz(t);
+          if ((tile_state<TJ, ODD>(t) >> b) & 1u)
+            L[b] = sw;
+          else
+            U[b] += sw - L[b];
+        }
+        sw += w[gp & 1][u];
+      }
+    }
   }
 #pragma unroll
   for (int i = 0; i < TJ; ++i)
@@ -147,17 +173,34 @@ __device__ inline void bond_chunk(const SiteTable<NC> &st, uint64_t x0, uint32_t
   }
 }
 
-// Wave total, taken from lane 0 (whose addition order is fixed).
+// One DPP move of a double (both 32-bit halves); lanes the pattern does not
+// write read 0.
+template <int CTRL, int ROW_MASK, bool BOUND_CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(bits)), CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(bits >> 32)), CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+  return __longlong_as_double(static_cast<long long>((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+// Sum over the wave's 64 lanes, valid in lane 63, by a fixed DPP tree on the
+// VALU (no LDS traffic): within each row of 16 lanes shifts by 1, 2, 4, 8 leave
+// the row total in its lane 15; row_bcast:15 adds row 0 into row 1 and row 2
+// into row 3, row_bcast:31 adds rows 0-1 into rows 2-3.
 __device__ __forceinline__ double wave_total(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v += dpp_f64<0x111, 0xf, true>(v);    // row_shr:1
+  v += dpp_f64<0x112, 0xf, true>(v);    // row_shr:2
+  v += dpp_f64<0x114, 0xf, true>(v);    // row_shr:4
+  v += dpp_f64<0x118, 0xf, true>(v);    // row_shr:8
+  v += dpp_f64<0x142, 0xa, false>(v);   // row_bcast:15
+  v += dpp_f64<0x143, 0xc, false>(v);   // row_bcast:31
   return v;
 }
 
 // Add every pair's chunk sum, summed over the wave, to the wave's accumulator.
 template <int TJ>
 __device__ inline void flush_pairs(const BondTables *__restrict__ T, const ChunkSums<TJ> &cs, uint64_t x0,
-                                   double *acc, bool lane0) {
+                                   double *acc, bool last_lane) {
 #pragma unroll
   for (int m = 0; m < kBwMid; ++m)
 #pragma unroll
@@ -165,7 +208,7 @@ __device__ inline void flush_pairs(const BondTables *__restrict__ T, const Chunk
       const int p = T->qpair[m][i];
       if (p >= 0) {
         const double v = wave_total(cs.Q[m][i]);
-        if (lane0) acc[p] += v;
+        if (last_lane) acc[p] += v;
       }
     }
 #pragma unroll
@@ -173,7 +216,7 @@ __device__ inline void flush_pairs(const BondTables *__restrict__ T, const Chunk
     const int p = T->m2pair[j];
     if (p >= 0) {
       const double v = wave_total(cs.M2[j]);
-      if (lane0) acc[p] += v;
+      if (last_lane) acc[p] += v;
     }
   }
 #pragma unroll
@@ -182,14 +225,14 @@ __device__ inline void flush_pairs(const BondTables *__restrict__ T, const Chunk
     const int e1 = T->ip_start[a + 1];
     for (int e = T->ip_start[a]; e < e1; ++e) {
       const double v = wave_total(((x0 >> T->ip_bit[e]) & 1u) ? V : -V);
-      if (lane0) acc[T->ip_pair[e]] += v;
+      if (last_lane) acc[T->ip_pair[e]] += v;
     }
   }
   const int n_pp = T->n_pp;
   for (int e = 0; e < n_pp; ++e) {
     const bool differ = (((x0 >> T->pp_a[e]) ^ (x0 >> T->pp_b[e])) & 1u) != 0;
     const double v = wave_total(differ ? -cs.S : cs.S);
-    if (lane0) acc[T->pp_pair[e]] += v;
+    if (last_lane) acc[T->pp_pair[e]] += v;
   }
 }
 
@@ -224,7 +267,7 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
     const uint64_t x0 = chunk << st.k;
     cs.clear();
     if (chunk < n_chunks) bond_chunk<TJ, NC>(st, x0, rep_bytes, wt, cs);
-    flush_pairs<TJ>(T, cs, x0, acc, lane == 0);
+    flush_pairs<TJ>(T, cs, x0, acc, lane == kWave - 1);
   }
   __syncthreads();
   for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
