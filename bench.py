@@ -93,6 +93,102 @@ def copy_calibration(nbytes: int) -> int:
     return 0
 
 
+def _median_ms(fn, reps: int) -> float:
+    """Median event-timed duration of fn() on the current stream, in ms."""
+    import numpy as np
+    import torch
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def bench_batched(plain_rate: float, reps: int) -> dict:
+    """The 256-lattice batch in one persistent launch, and the captured graph
+    of {zero, enumerate, moments}; reported beside the plain kernel."""
+    import torch
+
+    from paper_1110_2561_amd import api
+    from paper_1110_2561_amd import lattice as L
+    w = L.workload("batch256")
+    plan = api.BatchPlan(w["lattices"])
+    g = plan.new_tables()
+    api.batch_enumerate(plan, out=g)
+    torch.cuda.synchronize()
+    g_host = g.cpu()
+    for i, lat in enumerate(plan.lattices):   # every table sums to 2^N
+        assert int(plan.table(g_host, i).view(torch.int64).sum()) == 1 << lat.n_spins
+    total = plan.total_configs
+    ms = _median_ms(lambda: api.batch_enumerate(plan, out=g), reps)
+    graph = api.BatchGraph(plan, w["T"], w["h"])
+    graph.replay()
+    torch.cuda.synchronize()
+    gms = _median_ms(graph.replay, reps)
+    kinds = sorted({lat.kind for lat in plan.lattices})
+    return {
+        "workload": f"batch256: {len(plan)} lattices ({', '.join(kinds)}), N in "
+                    f"[{int(plan.n_spins.min())}, {int(plan.n_spins.max())}], J in {{-2,-1,1,2}}, one persistent launch",
+        "configs": total,
+        "value": total / (ms * 1e-3),
+        "unit": "configs/s",
+        "enumerate_ms": ms,
+        "graph_ms": gms,
+        "graph": f"zero + batched enumerate + batched moments on {len(w['T'])} T x {len(w['h'])} h",
+        "vs_plain": total / (ms * 1e-3) / plain_rate,
+    }
+
+
+def bench_autograd(plain_rate: float, reps: int) -> dict:
+    """log Z(T, h, J) on the 64 x 64 grid with its hand-written backward
+    (dT, dh from g; per-bond dJ by recomputed enumeration)."""
+    import torch
+
+    from paper_1110_2561_amd import api
+    from paper_1110_2561_amd import autograd as ag
+    from paper_1110_2561_amd import lattice as L
+    w = L.workload("autograd")
+    out = {"grid": [len(w["T"]), len(w["h"])], "dtype": "f64 sums over u32/u64 enumeration", "lattices": []}
+    for lat in w["lattices"]:
+        f = ag.IsingLogZ(lat)
+        T = torch.as_tensor(w["T"], dtype=torch.float64, device="cuda").requires_grad_(True)
+        h = torch.as_tensor(w["h"], dtype=torch.float64, device="cuda").requires_grad_(True)
+        J = f.couplings()
+        res = {}
+
+        def fwd():
+            res["lz"] = f(T, h, J)
+
+        def bwd():
+            res["g"] = torch.autograd.grad(res["lz"].sum(), (T, h, J), retain_graph=True)
+
+        fwd()
+        bwd()
+        torch.cuda.synchronize()
+        # sum rule: sum_b J_b d(sum log Z)/dJ_b = -sum_{T,h} <E>/T
+        m = api.moments(f.g, f.plan.e_min, lat.n_spins, T.detach(), h.detach())
+        lhs = float((J.detach() * res["g"][2]).sum())
+        rhs = float((-m["mean_E"] / T.detach()[:, None]).sum())
+        assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(rhs)), (lhs, rhs)
+        fms = _median_ms(fwd, reps)
+        bms = _median_ms(bwd, reps)
+        configs = 1 << lat.n_spins
+        out["lattices"].append({
+            "lattice": f"{lat.kind} {lat.describe()['dims']} (N={lat.n_spins}, {lat.n_bonds} bonds)",
+            "forward_ms": fms,
+            "backward_ms": bms,
+            "backward_value": configs / (bms * 1e-3),
+            "unit": "configs/s",
+            "vs_plain": configs / (bms * 1e-3) / plain_rate,
+        })
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +199,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-bits", type=int, default=0, help="plan tile width (0 = the plan's choice)")
     ap.add_argument("--inner-bits", type=int, default=0, help="plan chunk width (0 = the plan's choice)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and autograd measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -208,6 +305,9 @@ def main() -> int:
             "basis": "rocprofv3 SQ_INSTS_VALU_INT32 x 64 lanes per configuration, times the event-timed rate",
         },
     }
+    if not args.no_extras:
+        line["batched"] = bench_batched(achieved, reps=5)
+        line["autograd"] = bench_autograd(achieved, reps=3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(lat, args.cpu_sample_log2)
     print(json.dumps(line), flush=True)

@@ -6,7 +6,9 @@
 // product of every configuration; the enumeration is recomputed here in the
 // same Gray order as the forward walk, with FP64 sums in place of counts.
 //
-// Per lane and chunk (prefix fixed; k = tile + mj inner bits, mj <= 4):
+// Per lane and chunk (prefix fixed; k = tile + mj inner bits, mj <= 4; which
+// chunk of a task a thread takes is a planner table chosen so that lanes
+// sharing a weight-table copy read different LDS banks):
 //   * the tile walk (2^TJ configurations, only tile bits flip, fully
 //     unrolled) reads W of each configuration from an LDS copy of the table
 //     (one ds_read_b64 on the same running address as the forward's
@@ -261,9 +263,10 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
   SiteTable<NC> st;
   st.load(P, lane);
   const uint32_t rep_bytes = uint32_t(lane & (rw - 1)) * 8u;
+  const uint32_t offset = T->lane_chunk[threadIdx.x];
   ChunkSums<TJ> cs;
   for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
-    const uint64_t chunk = t * blockDim.x + threadIdx.x;
+    const uint64_t chunk = t * blockDim.x + offset;
     const uint64_t x0 = chunk << st.k;
     cs.clear();
     if (chunk < n_chunks) bond_chunk<TJ, NC>(st, x0, rep_bytes, wt, cs);

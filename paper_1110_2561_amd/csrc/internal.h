@@ -70,6 +70,7 @@ struct BondTables {
   uint8_t ip_bit[kMaxPairs];                // prefix bit of the entry
   int16_t pp_pair[kMaxPairs];
   uint8_t pp_a[kMaxPairs], pp_b[kMaxPairs];
+  uint16_t lane_chunk[kBwWaves * kWave];    // thread -> chunk offset within a task (a permutation)
 };
 
 }  // namespace ising

@@ -125,9 +125,13 @@ static void plan_backward(ising_plan *p, const ising_lattice *lat, const std::ve
     return;
   }
   const int n_pairs = (int)pairs.size();
+  // Weight-table row stride: a multiple of 4, so that bin mod 4 = n_up mod 4.
+  // A 64-bit LDS read serves 32 lanes per cycle from 32 banks of 8 bytes;
+  // double (bin * rw + copy) sits in bank (bin * rw + copy) mod 32.
+  const int Wb = (n + 4) & ~3;
   // weight-table copies that fit next to the per-wave pair accumulators
   const int64_t acc_bytes = int64_t(kBwWaves) * std::max(n_pairs, 1) * 8;
-  const int64_t copy_bytes = int64_t(d.n_ec) * d.W * 8;
+  const int64_t copy_bytes = int64_t(d.n_ec) * Wb * 8;
   int rw = 8;
   while (rw > 1 && copy_bytes * rw + acc_bytes > kHistBytes) rw >>= 1;
   if (copy_bytes * rw + acc_bytes > kHistBytes) {
@@ -137,6 +141,7 @@ static void plan_backward(ising_plan *p, const ising_lattice *lat, const std::ve
   }
   DevPlan &w = p->bw;
   w = d;
+  w.W = Wb;
   w.inner = kb;
   w.R = 2 * rw;   // row bytes W * R * 4 = W * rw * 8
   const int64_t row_bytes = int64_t(w.W) * w.R * 4, col_bytes = int64_t(w.R) * 4;
@@ -194,6 +199,34 @@ static void plan_backward(ising_plan *p, const ising_lattice *lat, const std::ve
       }
   }
   t.n_ip = e;
+
+  // Which chunk of a task each thread walks.  With 8 copies (copy = lane mod 8)
+  // the four lanes of a half-wave that share a copy must read four different
+  // bin mod 4 = n_up mod 4, i.e. chunks whose offsets have four different
+  // popcounts mod 4.  Offsets by popcount class are 136/136/120/120 of 512, so
+  // greedily give every copy group one offset of each class while they last
+  // (one half-wave of the 16 keeps a repeated class).  Other copy counts keep
+  // the identity.
+  const int nthreads = kBwWaves * kWave;
+  for (int i = 0; i < nthreads; ++i) t.lane_chunk[i] = (uint16_t)i;
+  if (rw == 8) {
+    std::vector<int> cls[4];
+    for (int o = 0; o < nthreads; ++o) cls[__builtin_popcount(unsigned(o)) & 3].push_back(o);
+    size_t next[4] = {0, 0, 0, 0};
+    auto left = [&](int c) { return cls[c].size() - next[c]; };
+    for (int h = 0; h < nthreads / 32; ++h)
+      for (int g = 0; g < 8; ++g) {
+        bool used[4] = {false, false, false, false};
+        for (int j = 0; j < 4; ++j) {
+          int best = -1;
+          for (int pass = 0; pass < 2 && best < 0; ++pass)
+            for (int c = 0; c < 4; ++c)
+              if (left(c) > 0 && (pass == 1 || !used[c]) && (best < 0 || left(c) > left(best))) best = c;
+          used[best] = true;
+          t.lane_chunk[h * 32 + g + 8 * j] = (uint16_t)cls[best][next[best]++];
+        }
+      }
+  }
 }
 
 extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_tune *tune,
