@@ -119,6 +119,16 @@ ising_status ising_enumerate(const ising_plan *plan, uint64_t *g_dev, void *stre
 ising_status ising_enumerate_range(const ising_plan *plan, uint64_t first_chunk,
                                    uint64_t n_chunks, uint64_t *g_dev, void *stream);
 
+/* The same table as ising_enumerate, from half of the configurations: every
+ * H of Eq. (1) at h = 0 is even in the spins, so a global spin flip maps
+ * (E, M) to (E, -M) and g(E, M) = g(E, -M).  This enumerates the
+ * configurations whose top plan bit (a prefix spin) is up, i.e. chunks
+ * [n_chunks/2, n_chunks), then sets g(E, M) to the sum of their counts at M
+ * and -M.  2^(N-1) configurations are enumerated for 2^N covered.  Plans with
+ * a single chunk fall back to the full enumeration.  g_dev as in
+ * ising_enumerate (overwritten). */
+ising_status ising_enumerate_symmetric(const ising_plan *plan, uint64_t *g_dev, void *stream);
+
 /* log Z(T, h) of Eq. (2) in FP64 from a dense table on the device:
  *   logz[a * nh + b] = log sum_{g>0} g(E,M) exp(-(E - h_b M)/T_a).
  * g_dev: [n_e][n_m] uint64 with n_m = n_spins + 1 and e_min its first energy.

@@ -59,6 +59,7 @@ ising_hist_shape = _sig("ising_hist_shape", i32, vp, i32p, i32p, i32p)
 ising_plan_layout = _sig("ising_plan_layout", i32, vp, i32p, i32p, i32p, u64p)
 ising_enumerate = _sig("ising_enumerate", i32, vp, vp, vp)
 ising_enumerate_range = _sig("ising_enumerate_range", i32, vp, u64, u64, vp, vp)
+ising_enumerate_symmetric = _sig("ising_enumerate_symmetric", i32, vp, vp, vp)
 ising_logz = _sig("ising_logz", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp)
 ising_moments = _sig("ising_moments", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp)
 ising_logz_derivatives = _sig("ising_logz_derivatives", i32, vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp, vp,

@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from .lattice import Lattice
 
-__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_range", "log_z", "moments", "IsingError",
+__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_symmetric", "enumerate_range", "log_z", "moments", "IsingError",
            "logz_derivatives", "bin_weights", "bond_backward",
            "BatchPlan", "batch_enumerate", "batch_moments", "BatchGraph"]
 
@@ -108,6 +108,15 @@ def enumerate_g(plan: Plan, out: torch.Tensor | None = None, stream=None) -> tor
     g = plan.new_table() if out is None else out
     _check_table(plan, g)
     _lib.check(_lib.ising_enumerate(plan.handle, g.data_ptr(), _stream_handle(stream)))
+    return g
+
+
+def enumerate_symmetric(plan: Plan, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """g(E, M) from the half of the configurations with the top plan bit up,
+    mirrored M -> -M (ising_enumerate_symmetric); equal to enumerate_g."""
+    g = plan.new_table() if out is None else out
+    _check_table(plan, g)
+    _lib.check(_lib.ising_enumerate_symmetric(plan.handle, g.data_ptr(), _stream_handle(stream)))
     return g
 
 

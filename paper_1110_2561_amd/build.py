@@ -19,7 +19,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libising.so")
-SOURCES = ["plan.cpp", "enumerate.hip", "thermo.hip", "batch.hip", "bond.hip"]
+SOURCES = ["plan.cpp", "bond_plan.cpp", "enumerate.hip", "thermo.hip", "batch.hip", "bond.hip"]
 ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -36,6 +36,7 @@
 #include <cstring>
 #include <string>
 
+#include "bond.h"
 #include "internal.h"
 #include "walk.h"
 
@@ -299,15 +300,16 @@ static void *bond_device_tables(ising_plan *p, int device, ising_status *st) {
     *st = fail(ISING_EUNSUPPORTED, "device index out of range");
     return nullptr;
   }
+  BondPlan *bp = p->bond;
   std::lock_guard<std::mutex> lk(p->mu);
-  if (!p->bw_copy[device]) {
-    const size_t bytes = sizeof(DevPlan) + sizeof(BondTables) + p->pair_of_bond.size() * sizeof(int32_t);
+  if (!bp->dev_copy[device]) {
+    const size_t bytes = sizeof(DevPlan) + sizeof(BondTables) + bp->pair_of_bond.size() * sizeof(int32_t);
     std::vector<char> host(bytes);
-    std::memcpy(host.data(), &p->bw, sizeof(DevPlan));
-    std::memcpy(host.data() + sizeof(DevPlan), &p->bt, sizeof(BondTables));
-    if (!p->pair_of_bond.empty())
-      std::memcpy(host.data() + sizeof(DevPlan) + sizeof(BondTables), p->pair_of_bond.data(),
-                  p->pair_of_bond.size() * sizeof(int32_t));
+    std::memcpy(host.data(), &bp->geo, sizeof(DevPlan));
+    std::memcpy(host.data() + sizeof(DevPlan), &bp->tables, sizeof(BondTables));
+    if (!bp->pair_of_bond.empty())
+      std::memcpy(host.data() + sizeof(DevPlan) + sizeof(BondTables), bp->pair_of_bond.data(),
+                  bp->pair_of_bond.size() * sizeof(int32_t));
     void *ptr = nullptr;
     hipError_t e = hipMalloc(&ptr, bytes);
     if (e != hipSuccess) {
@@ -320,9 +322,16 @@ static void *bond_device_tables(ising_plan *p, int device, ising_status *st) {
       *st = fail(ISING_EHIP, std::string("hipMemcpy(backward tables): ") + hipGetErrorString(e));
       return nullptr;
     }
-    p->bw_copy[device] = ptr;
+    bp->dev_copy[device] = ptr;
   }
-  return p->bw_copy[device];
+  return bp->dev_copy[device];
+}
+
+void bond_plan_free(BondPlan *b) {
+  if (!b) return;
+  for (int d = 0; d < kMaxDevices; ++d)
+    if (b->dev_copy[d]) (void)hipFree(b->dev_copy[d]);
+  delete b;
 }
 
 template <int TJ, int NC>
@@ -364,15 +373,16 @@ using namespace ising;
 
 extern "C" ising_status ising_bond_workspace(const ising_plan *p, size_t *bytes) {
   if (!p || !bytes) return fail(ISING_EINVAL, "plan or bytes is NULL");
-  if (p->bw_status != ISING_OK) return fail(p->bw_status, p->bw_error);
-  *bytes = size_t(kMaxBwBlocks) * size_t(std::max(p->bt.n_pairs, 1)) * sizeof(double);
+  if (p->bond->status != ISING_OK) return fail(p->bond->status, p->bond->error);
+  *bytes = size_t(kMaxBwBlocks) * size_t(std::max(p->bond->tables.n_pairs, 1)) * sizeof(double);
   return ISING_OK;
 }
 
 extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev,
                                             void *workspace, size_t workspace_bytes, void *stream) {
   if (!pc) return fail(ISING_EINVAL, "plan is NULL");
-  if (pc->bw_status != ISING_OK) return fail(pc->bw_status, pc->bw_error);
+  const BondPlan *bp = pc->bond;
+  if (bp->status != ISING_OK) return fail(bp->status, bp->error);
   if (pc->n_bonds == 0) return ISING_OK;
   if (!W_dev || !dJ_dev || !workspace) return fail(ISING_EINVAL, "W_dev, dJ_dev or workspace is NULL");
   size_t need = 0;
@@ -391,13 +401,13 @@ extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *
   const int32_t *dmap = reinterpret_cast<const int32_t *>(tables + sizeof(DevPlan) + sizeof(BondTables));
   int cus = 0;
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const uint64_t n_chunks = uint64_t(1) << (p->bw.n - p->bw.inner);
+  const uint64_t n_chunks = uint64_t(1) << (bp->geo.n - bp->geo.inner);
   const uint64_t block = uint64_t(kBwWaves) * kWave;
   const uint64_t n_tasks = (n_chunks + block - 1) / block;
   const int grid = int(std::min<uint64_t>({n_tasks, uint64_t(cus), uint64_t(kMaxBwBlocks)}));
   hipStream_t s = static_cast<hipStream_t>(stream);
   double *partial = static_cast<double *>(workspace);
-  st = bond_dispatch(p->bw.tile, p->bw.n_classes, dP, dT, W_dev, n_chunks, n_tasks, grid, partial, s);
+  st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, dP, dT, W_dev, n_chunks, n_tasks, grid, partial, s);
   if (st != ISING_OK) return st;
   const int fb = std::min((p->n_bonds + 255) / 256, 1024);
   hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(fb)), dim3(256), 0, s, dT, dmap, partial, grid, dJ_dev);

@@ -33,6 +33,7 @@
 //     atomic rate (one ds_add_u32 per configuration).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "internal.h"
@@ -81,6 +82,24 @@ __global__ __launch_bounds__(1024) void k_enumerate(const DevPlan *__restrict__ 
   }
   __syncthreads();
   flush_hist(P, h32, g);
+}
+
+// g(E, M) = g(E, -M) for every coupling set (H at h = 0 is even in the spins),
+// and the configurations with the top plan bit down are the spin flips of
+// those with it up.  So from h_up, the table of the upper half of the chunk
+// range, g[e][nu] = h_up[e][nu] + h_up[e][N - nu]; done in place, one thread
+// per (e, nu <= N - nu) pair.
+__global__ void k_mirror_u64(unsigned long long *g, int n_e, int n_m) {
+  const int half = (n_m + 1) / 2;   // nu in [0, half) pairs with n_m - 1 - nu
+  const size_t cells = size_t(n_e) * half;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < cells; i += size_t(gridDim.x) * blockDim.x) {
+    const size_t e = i / half;
+    const int nu = int(i - e * half), mu = n_m - 1 - nu;
+    unsigned long long *row = g + e * n_m;
+    const unsigned long long s = row[nu] + row[mu];
+    row[nu] = s;
+    row[mu] = s;
+  }
 }
 
 __global__ void k_fill_u64(unsigned long long *p, size_t n) {
@@ -182,10 +201,9 @@ using namespace ising;
 
 extern "C" ising_status ising_plan_destroy(ising_plan *p) {
   if (!p) return ISING_OK;
-  for (int d = 0; d < kMaxDevices; ++d) {
+  for (int d = 0; d < kMaxDevices; ++d)
     if (p->dev_copy[d]) (void)hipFree(p->dev_copy[d]);
-    if (p->bw_copy[d]) (void)hipFree(p->bw_copy[d]);
-  }
+  bond_plan_free(p->bond);
   delete p;
   return ISING_OK;
 }
@@ -208,4 +226,24 @@ extern "C" ising_status ising_enumerate_range(const ising_plan *p, uint64_t firs
   if (first_chunk > p->n_chunks || n_chunks > p->n_chunks - first_chunk)
     return fail(ISING_EINVAL, "chunk range exceeds the plan's " + std::to_string(p->n_chunks) + " chunks");
   return enumerate_chunks(p, first_chunk, n_chunks, g_dev, static_cast<hipStream_t>(stream));
+}
+
+extern "C" ising_status ising_enumerate_symmetric(const ising_plan *p, uint64_t *g_dev, void *stream) {
+  if (!p || !g_dev) return fail(ISING_EINVAL, "plan or g_dev is NULL");
+  if (p->n_chunks < 2) return ising_enumerate(p, g_dev, stream);   // the top bit is not a prefix bit
+  const size_t cells = size_t(2 * p->S + 1) * size_t(p->n_spins + 1);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int threads = 256;
+  hipLaunchKernelGGL(k_fill_u64, dim3(unsigned(std::min<size_t>((cells + threads - 1) / threads, 4096))),
+                     dim3(threads), 0, s, reinterpret_cast<unsigned long long *>(g_dev), cells);
+  HIP_TRY(hipGetLastError());
+  const uint64_t half = p->n_chunks / 2;   // chunks [half, n_chunks): top plan bit up
+  ising_status st = enumerate_chunks(p, half, half, g_dev, s);
+  if (st != ISING_OK) return st;
+  const int n_e = int(2 * p->S + 1), n_m = p->n_spins + 1;
+  const size_t pairs = size_t(n_e) * size_t((n_m + 1) / 2);
+  hipLaunchKernelGGL(k_mirror_u64, dim3(unsigned(std::min<size_t>((pairs + threads - 1) / threads, 4096))),
+                     dim3(threads), 0, s, reinterpret_cast<unsigned long long *>(g_dev), n_e, n_m);
+  HIP_TRY(hipGetLastError());
+  return ISING_OK;
 }

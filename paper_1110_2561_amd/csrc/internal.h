@@ -11,6 +11,8 @@
 
 namespace ising {
 
+struct BondPlan;   // per-bond backward plan (bond.h)
+
 constexpr int kMaxSpins = 64;
 constexpr int kMaxClasses = 8;      // distinct nonzero merged couplings
 constexpr int kMaxTile = 8;         // tile bits j (independent-set spins)
@@ -20,9 +22,6 @@ constexpr int kLdsBytes = 160 * 1024;
 constexpr int kHistBytes = kLdsBytes - 64;   // LDS histogram; the rest holds block control words
 constexpr int kWave = 64;
 constexpr int kMaxDevices = 64;
-constexpr int kMaxPairs = 512;      // distinct bond pairs the per-bond backward handles
-constexpr int kBwMid = 4;           // middle bits of the backward walk (at most)
-constexpr int kBwWaves = 8;         // waves per block of the backward kernel
 
 // Constants one enumeration launch reads (uploaded once per device).
 // Spin indices are plan bit positions: bits [0, tile) are the tile (an
@@ -52,27 +51,6 @@ struct DevPlan {
   uint64_t mask[kMaxSpins][kMaxClasses];    // neighbours of bit i with coupling class c
 };
 
-// Where each distinct bond pair of the lattice sits in the backward walk
-// (bit positions of the backward geometry: tile [0, TJ), middle [TJ, TJ + mj),
-// prefix above), and where its per-chunk sum comes from.
-struct BondTables {
-  int32_t n_pairs;       // distinct bond pairs
-  int32_t mj;            // middle bits
-  int32_t n_ip, n_pp;    // inner-prefix and prefix-prefix pairs
-  int32_t rw;            // copies of the FP64 weight table in LDS
-  int32_t wt_bytes;      // LDS bytes of the weight table (all copies)
-  int32_t n_bonds;       // input bonds (pair_of_bond entries after this struct)
-  int32_t pad;
-  int16_t qpair[kBwMid][kMaxTile];          // tile t - middle m pair, or -1
-  int16_t m2pair[6];                        // middle pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3), or -1
-  int16_t ip_start[kMaxTile + kBwMid + 1];  // inner bit a: entries [ip_start[a], ip_start[a+1])
-  int16_t ip_pair[kMaxPairs];
-  uint8_t ip_bit[kMaxPairs];                // prefix bit of the entry
-  int16_t pp_pair[kMaxPairs];
-  uint8_t pp_a[kMaxPairs], pp_b[kMaxPairs];
-  uint16_t lane_chunk[kBwWaves * kWave];    // thread -> chunk offset within a task (a permutation)
-};
-
 }  // namespace ising
 
 struct ising_plan {
@@ -92,15 +70,8 @@ struct ising_plan {
   // per-device constant copies (lazy)
   std::mutex mu;
   void *dev_copy[ising::kMaxDevices] = {};
-  // per-bond backward: its walk geometry (same bit order, k = tile + middle,
-  // byte constants for the FP64 weight table), pair tables, input bond ->
-  // pair map, and per-device copies of {DevPlan, BondTables, pair_of_bond}
-  ising::DevPlan bw{};
-  ising::BondTables bt{};
-  std::vector<int32_t> pair_of_bond;
-  ising_status bw_status = ISING_OK;
-  std::string bw_error;
-  void *bw_copy[ising::kMaxDevices] = {};
+  // per-bond backward (bond.h), built with the plan; null if its set-up failed
+  ising::BondPlan *bond = nullptr;
 };
 
 namespace ising {
@@ -128,6 +99,11 @@ ising_status plan_create_internal(const ising_lattice *lat, const ising_tune *tu
                                   ising_plan **out, bool exact_tile = true);
 ising_status fail(ising_status st, const std::string &msg);
 const void *plan_device_constants(ising_plan *plan, int device, ising_status *st);
+// per-bond backward plan of a finished forward plan (bond_plan.cpp); J is the
+// merged n x n coupling matrix, classes the distinct merged couplings
+BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const std::vector<int64_t> &J,
+                           const std::vector<int64_t> &classes);
+void bond_plan_free(BondPlan *b);   // frees its device copies too (bond.hip)
 }  // namespace ising
 
 struct ising_batch_plan {

@@ -91,144 +91,6 @@ static void place_lane_spins(int n, int k, int R, const std::vector<int64_t> &J,
   while (ie < even_sites.size()) *dst++ = even_sites[ie++];
 }
 
-// Geometry and pair tables of the per-bond backward walk (see bond.hip).  It
-// keeps the forward bit order: tile bits [0, TJ), then mj <= 4 middle bits,
-// the rest prefix.  Pairs are the distinct (i, j) of the input bonds, also
-// those whose couplings cancel (their spin products still have averages).  Byte constants address an FP64 weight table with rw
-// interleaved copies: word (bin * rw + copy), bin = e_idx * W + n_up.
-static void plan_backward(ising_plan *p, const ising_lattice *lat, const std::vector<int64_t> &J,
-                          const std::vector<int64_t> &classes) {
-  const DevPlan &d = p->dev;
-  const int n = d.n, TJ = d.tile;
-  const int mj = std::min(kBwMid, n - TJ);
-  const int kb = TJ + mj;
-  auto bad = [&](const std::string &m) {
-    p->bw_status = ISING_EUNSUPPORTED;
-    p->bw_error = m;
-  };
-  // distinct pairs in order of first appearance among the input bonds
-  std::vector<int32_t> pid(size_t(n) * n, -1);
-  std::vector<std::pair<int, int>> pairs;
-  p->pair_of_bond.assign(size_t(lat->n_bonds), -1);
-  for (int b = 0; b < lat->n_bonds; ++b) {
-    const int i = std::min(lat->bond_i[b], lat->bond_j[b]), j = std::max(lat->bond_i[b], lat->bond_j[b]);
-    int32_t &slot = pid[size_t(i) * n + j];
-    if (slot < 0) {
-      slot = int32_t(pairs.size());
-      pairs.push_back({i, j});
-    }
-    p->pair_of_bond[b] = slot;
-  }
-  if ((int)pairs.size() > kMaxPairs) {
-    bad(std::to_string(pairs.size()) + " distinct coupled pairs (the backward handles " +
-        std::to_string(kMaxPairs) + ")");
-    return;
-  }
-  const int n_pairs = (int)pairs.size();
-  // Weight-table row stride: a multiple of 4, so that bin mod 4 = n_up mod 4.
-  // A 64-bit LDS read serves 32 lanes per cycle from 32 banks of 8 bytes;
-  // double (bin * rw + copy) sits in bank (bin * rw + copy) mod 32.
-  const int Wb = (n + 4) & ~3;
-  // weight-table copies that fit next to the per-wave pair accumulators
-  const int64_t acc_bytes = int64_t(kBwWaves) * std::max(n_pairs, 1) * 8;
-  const int64_t copy_bytes = int64_t(d.n_ec) * Wb * 8;
-  int rw = 8;
-  while (rw > 1 && copy_bytes * rw + acc_bytes > kHistBytes) rw >>= 1;
-  if (copy_bytes * rw + acc_bytes > kHistBytes) {
-    bad("FP64 weight table of " + std::to_string(d.n_ec) + " x " + std::to_string(d.W) +
-        " bins does not fit the LDS");
-    return;
-  }
-  DevPlan &w = p->bw;
-  w = d;
-  w.W = Wb;
-  w.inner = kb;
-  w.R = 2 * rw;   // row bytes W * R * 4 = W * rw * 8
-  const int64_t row_bytes = int64_t(w.W) * w.R * 4, col_bytes = int64_t(w.R) * 4;
-  for (int c = 0; c < (int)classes.size(); ++c)
-    w.cls_step[c] = (int32_t)((4 * classes[c] / w.estep) * row_bytes);
-  for (int b = 0; b < n; ++b) w.up_base[b] = (int32_t)((2 * int64_t(w.hdeg[b]) / w.estep) * row_bytes + col_bytes);
-  std::memset(w.kmid, 0, sizeof(w.kmid));
-  for (int m = TJ; m < kb; ++m)
-    for (int i = 0; i < TJ; ++i) {
-      const int64_t v = J[size_t(p->site_of_bit[m]) * n + p->site_of_bit[i]];
-      w.kmid[m - TJ][i] = (int32_t)((-4 * v / w.estep) * row_bytes);
-    }
-
-  BondTables &t = p->bt;
-  t = BondTables{};
-  t.n_pairs = n_pairs;
-  t.mj = mj;
-  t.rw = rw;
-  t.wt_bytes = (int32_t)(copy_bytes * rw);
-  t.n_bonds = lat->n_bonds;
-  for (auto &row : t.qpair)
-    for (auto &v : row) v = -1;
-  for (auto &v : t.m2pair) v = -1;
-  std::vector<std::vector<std::pair<int, int>>> ip(static_cast<size_t>(kb));   // inner bit -> (pair, prefix bit)
-  for (int q = 0; q < n_pairs; ++q) {
-    int a = p->bit_of_site[pairs[q].first], b = p->bit_of_site[pairs[q].second];
-    if (a > b) std::swap(a, b);
-    if (b < TJ) {   // the tile holds no listed pair
-      bad("internal: bond pair inside the tile");
-      return;
-    }
-    if (b < kb) {
-      if (a < TJ) t.qpair[b - TJ][a] = (int16_t)q;
-      else {
-        const int m1 = a - TJ, m2 = b - TJ;
-        t.m2pair[m1 * (7 - m1) / 2 + (m2 - m1 - 1)] = (int16_t)q;
-      }
-    } else if (a < kb) {
-      ip[size_t(a)].push_back({q, b});
-    } else {
-      t.pp_pair[t.n_pp] = (int16_t)q;
-      t.pp_a[t.n_pp] = (uint8_t)a;
-      t.pp_b[t.n_pp] = (uint8_t)b;
-      ++t.n_pp;
-    }
-  }
-  int e = 0;
-  for (int a = 0; a <= kMaxTile + kBwMid; ++a) {
-    t.ip_start[a] = (int16_t)e;
-    if (a < kb)
-      for (auto &pr : ip[size_t(a)]) {
-        t.ip_pair[e] = (int16_t)pr.first;
-        t.ip_bit[e] = (uint8_t)pr.second;
-        ++e;
-      }
-  }
-  t.n_ip = e;
-
-  // Which chunk of a task each thread walks.  With 8 copies (copy = lane mod 8)
-  // the four lanes of a half-wave that share a copy must read four different
-  // bin mod 4 = n_up mod 4, i.e. chunks whose offsets have four different
-  // popcounts mod 4.  Offsets by popcount class are 136/136/120/120 of 512, so
-  // greedily give every copy group one offset of each class while they last
-  // (one half-wave of the 16 keeps a repeated class).  Other copy counts keep
-  // the identity.
-  const int nthreads = kBwWaves * kWave;
-  for (int i = 0; i < nthreads; ++i) t.lane_chunk[i] = (uint16_t)i;
-  if (rw == 8) {
-    std::vector<int> cls[4];
-    for (int o = 0; o < nthreads; ++o) cls[__builtin_popcount(unsigned(o)) & 3].push_back(o);
-    size_t next[4] = {0, 0, 0, 0};
-    auto left = [&](int c) { return cls[c].size() - next[c]; };
-    for (int h = 0; h < nthreads / 32; ++h)
-      for (int g = 0; g < 8; ++g) {
-        bool used[4] = {false, false, false, false};
-        for (int j = 0; j < 4; ++j) {
-          int best = -1;
-          for (int pass = 0; pass < 2 && best < 0; ++pass)
-            for (int c = 0; c < 4; ++c)
-              if (left(c) > 0 && (pass == 1 || !used[c]) && (best < 0 || left(c) > left(best))) best = c;
-          used[best] = true;
-          t.lane_chunk[h * 32 + g + 8 * j] = (uint16_t)cls[best][next[best]++];
-        }
-      }
-  }
-}
-
 extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_tune *tune,
                                           ising_plan **out) {
   return ising::plan_create_internal(lat, tune, 1, out);
@@ -439,7 +301,11 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
       // tile spin i's up-flip delta, in bytes, changes by this when bit m goes up
       d.kmid[m - TJ][i] = (int32_t)((-4 * v / estep) * row_bytes);
     }
-  plan_backward(p, lat, J, classes);
+  p->bond = bond_plan_create(p, lat, J, classes);
+  if (!p->bond) {
+    delete p;
+    return fail(ISING_ENOMEM, "plan allocation");
+  }
   *out = p;
   set_error("");
   return ISING_OK;

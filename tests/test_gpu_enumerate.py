@@ -170,3 +170,25 @@ def test_side_stream(api):
         g = api.enumerate_g(plan, stream=s)
     s.synchronize()
     np.testing.assert_array_equal(g.cpu().numpy(), _bf(lat))
+
+
+# --------------------------------------------------------------------------
+# spin-flip halving: half the configurations, mirrored M -> -M
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lat,tune", SMALL, ids=[f"{l.kind}{l.n_spins}-{i}" for i, (l, _) in enumerate(SMALL)])
+def test_symmetric_small_systems_bit_exact(api, lat, tune):
+    print(f"symmetric case {lat.kind} N={lat.n_spins} tune={tune}", flush=True)
+    plan = api.Plan(lat, api.Tune(**tune) if tune else None)
+    g = plan.new_table()
+    g.fill_(12345)                                          # stale contents must be overwritten
+    api.enumerate_symmetric(plan, out=g)
+    np.testing.assert_array_equal(g.cpu().numpy(), _bf(lat))
+
+
+@pytest.mark.parametrize("name", ["torus6x6", "torus8x5_pm"])
+def test_symmetric_full_size_matches_transfer_matrix(api, name):
+    lat = L.workload(name)["lattice"]
+    plan = api.Plan(lat)
+    g = api.enumerate_symmetric(plan).cpu().numpy()
+    np.testing.assert_array_equal(g, _tm(lat))
