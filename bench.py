@@ -144,6 +144,26 @@ def bench_batched(plain_rate: float, reps: int) -> dict:
     }
 
 
+def bench_symmetric(plan, g, configs: int, plain_rate: float, reps: int) -> dict:
+    """The same table from half the configurations (global spin flip,
+    g(E, M) = g(E, -M)); configurations covered vs enumerated reported apart."""
+    import torch
+
+    from paper_1110_2561_amd import api
+    ref = g.clone()
+    api.enumerate_symmetric(plan, out=g)
+    torch.cuda.synchronize()
+    assert torch.equal(g, ref), "halved table differs from the full enumeration"
+    ms = _median_ms(lambda: api.enumerate_symmetric(plan, out=g), reps)
+    return {
+        "method": "enumerate the configurations with the top prefix spin up, then g(E,M) += g(E,-M)",
+        "ms": ms,
+        "configs_covered_per_s": configs / (ms * 1e-3),
+        "configs_enumerated_per_s": configs / 2 / (ms * 1e-3),
+        "vs_plain": configs / (ms * 1e-3) / plain_rate,
+    }
+
+
 def bench_autograd(plain_rate: float, reps: int) -> dict:
     """log Z(T, h, J) on the 64 x 64 grid with its hand-written backward
     (dT, dh from g; per-bond dJ by recomputed enumeration)."""
@@ -306,6 +326,7 @@ def main() -> int:
         },
     }
     if not args.no_extras:
+        line["z2_halving"] = bench_symmetric(plan, g, configs, achieved, reps=5)
         line["batched"] = bench_batched(achieved, reps=5)
         line["autograd"] = bench_autograd(achieved, reps=3)
     if not args.no_cpu_baseline:

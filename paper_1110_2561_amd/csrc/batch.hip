@@ -53,6 +53,7 @@ __global__ __launch_bounds__(1024) void k_batch_enumerate(const DevPlan *__restr
   for (int w = threadIdx.x; w < kHistBytes / 4; w += blockDim.x) h32[w] = 0;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   SiteTable<NC> st;
+  uint32_t offset = threadIdx.x;
   int cur = -1;
   uint32_t since = 0, it = 0;
   for (;; ++it) {
@@ -72,11 +73,12 @@ __global__ __launch_bounds__(1024) void k_batch_enumerate(const DevPlan *__restr
       if (un.inst != cur) {
         cur = un.inst;
         st.load(&plans[cur], int(lane));
+        offset = plans[cur].lane_chunk[threadIdx.x];
       }
       since = 0;
     }
     const DevPlan *P = &plans[cur];
-    const uint64_t chunk = un.task * blockDim.x + threadIdx.x;
+    const uint64_t chunk = un.task * blockDim.x + offset;
     if (chunk < meta[cur].n_chunks) {
       const uint32_t rep = lane_copy(lane, P->R);
       switch (P->tile) {  // uniform: each member keeps its own tile width

@@ -115,33 +115,11 @@ BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const 
   }
   t.n_ip = e;
 
-  // Which chunk of a task each thread walks.  With 8 copies (copy = lane mod 8)
-  // the four lanes of a half-wave that share a copy must read four different
-  // bin mod 4 = n_up mod 4, i.e. chunks whose offsets have four different
-  // popcounts mod 4.  Offsets by popcount class are 136/136/120/120 of 512, so
-  // greedily give every copy group one offset of each class while they last
-  // (one half-wave of the 16 keeps a repeated class).  Other copy counts keep
-  // the identity.
+  // Which chunk of a task each thread walks: with 8 copies, lanes sharing a
+  // copy get chunks of four different n_up mod 4 (balance_lane_chunks).
   const int nthreads = kBwWaves * kWave;
   for (int i = 0; i < nthreads; ++i) t.lane_chunk[i] = (uint16_t)i;
-  if (rw == 8) {
-    std::vector<int> cls[4];
-    for (int o = 0; o < nthreads; ++o) cls[__builtin_popcount(unsigned(o)) & 3].push_back(o);
-    size_t next[4] = {0, 0, 0, 0};
-    auto left = [&](int c) { return cls[c].size() - next[c]; };
-    for (int h = 0; h < nthreads / 32; ++h)
-      for (int g = 0; g < 8; ++g) {
-        bool used[4] = {false, false, false, false};
-        for (int j = 0; j < 4; ++j) {
-          int best = -1;
-          for (int pass = 0; pass < 2 && best < 0; ++pass)
-            for (int c = 0; c < 4; ++c)
-              if (left(c) > 0 && (pass == 1 || !used[c]) && (best < 0 || left(c) > left(best))) best = c;
-          used[best] = true;
-          t.lane_chunk[h * 32 + g + 8 * j] = (uint16_t)cls[best][next[best]++];
-        }
-      }
-  }
+  if (rw == 8) balance_lane_chunks(t.lane_chunk, nthreads);
   return bp;
 }
 

@@ -48,12 +48,16 @@ namespace ising {
   } while (0)
 
 // Task t of this block covers chunks (task_lo + t) * blockDim.x + [0, blockDim.x),
-// one per thread; lanes whose chunk lies outside [chunk_lo, chunk_hi) idle.
-// Lanes l and l + 16 of a half-wave share LDS copy l mod 16; their chunks
-// differ in one prefix spin, so their n_up differ by one, and with an even
-// row stride W their words fall in different banks (bank = 16 * (bin mod 2)
-// + copy on the 32-bank LDS).  All threads of a block run the
-// same number of tasks, so the barriers around periodic flushes are uniform.
+// one per thread (thread -> offset by the plan's lane_chunk permutation);
+// lanes whose chunk lies outside [chunk_lo, chunk_hi) idle.  With 16 copies
+// (identity permutation) lanes l and l + 16 of a half-wave share LDS copy
+// l mod 16; their chunks differ in one prefix spin, so their n_up differ by
+// one, and with an even row stride W their words fall in different banks
+// (bank = 16 * (bin mod 2) + copy on the 32-bank LDS).  With 8 copies the
+// permutation gives the four lanes sharing a copy four n_up mod 4 and the
+// stride is a multiple of 4 (bank = 8 * (bin mod 4) + copy).  All threads
+// of a block run the same number of tasks, so the barriers around periodic
+// flushes are uniform.
 template <int TJ, int NC>
 __global__ __launch_bounds__(1024) void k_enumerate(const DevPlan *__restrict__ P, uint64_t chunk_lo,
                                                     uint64_t chunk_hi, uint64_t task_lo, uint64_t n_tasks,
@@ -69,9 +73,10 @@ __global__ __launch_bounds__(1024) void k_enumerate(const DevPlan *__restrict__ 
   const uint32_t rep = lane_copy(lane, P->R);
   SiteTable<NC> st;
   st.load(P, int(lane));
+  const uint32_t offset = P->lane_chunk[threadIdx.x];
   uint32_t since = 0;
   for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
-    const uint64_t chunk = (task_lo + t) * blockDim.x + threadIdx.x;
+    const uint64_t chunk = (task_lo + t) * blockDim.x + offset;
     if (chunk >= chunk_lo && chunk < chunk_hi) walk_chunk<TJ, NC>(st, chunk, rep, hist);
     if (++since == flush_every) {
       __syncthreads();

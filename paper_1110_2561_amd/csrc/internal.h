@@ -21,6 +21,7 @@ constexpr int kMaxMiddle = kMaxInner - 1;
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kHistBytes = kLdsBytes - 64;   // LDS histogram; the rest holds block control words
 constexpr int kWave = 64;
+constexpr int kMaxBlockThreads = 1024;
 constexpr int kMaxDevices = 64;
 
 // Constants one enumeration launch reads (uploaded once per device).
@@ -49,6 +50,9 @@ struct DevPlan {
   int32_t hdeg[kMaxSpins];                  // sum_c J_c * deg_c(b)
   int32_t kmid[kMaxMiddle][kMaxTile];       // byte change of tile delta i when middle bit m goes up
   uint64_t mask[kMaxSpins][kMaxClasses];    // neighbours of bit i with coupling class c
+  // Thread t of a block walks chunk task * blockDim + lane_chunk[t] (a
+  // permutation of the block's chunk offsets; see balance_lane_chunks).
+  uint16_t lane_chunk[kMaxBlockThreads];
 };
 
 }  // namespace ising
@@ -99,6 +103,10 @@ ising_status plan_create_internal(const ising_lattice *lat, const ising_tune *tu
                                   ising_plan **out, bool exact_tile = true);
 ising_status fail(ising_status st, const std::string &msg);
 const void *plan_device_constants(ising_plan *plan, int device, ising_status *st);
+// Thread -> chunk-offset permutation of a block of `threads` (a multiple of
+// 32) for histograms or tables kept in 8 interleaved LDS copies (copy = lane
+// mod 8) with a row stride that is a multiple of 4 (plan.cpp).
+void balance_lane_chunks(uint16_t *lane_chunk, int threads);
 // per-bond backward plan of a finished forward plan (bond_plan.cpp); J is the
 // merged n x n coupling matrix, classes the distinct merged couplings
 BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const std::vector<int64_t> &J,

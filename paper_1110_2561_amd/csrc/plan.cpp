@@ -91,6 +91,33 @@ static void place_lane_spins(int n, int k, int R, const std::vector<int64_t> &J,
   while (ie < even_sites.size()) *dst++ = even_sites[ie++];
 }
 
+// Thread -> chunk offset for 8 interleaved LDS copies (copy = lane mod 8).
+// The four lanes of a half-wave that share a copy hit four different banks
+// when their chunks' n_up differ mod 4, i.e. when the popcounts of their
+// chunk offsets (the prefix spins that tell a block's lanes apart) differ
+// mod 4.  Offsets by popcount class are not equally many (for 2^m offsets
+// the class sizes differ by about 2^(m/2)), so greedily give every copy group
+// one offset of each class while the classes last; the few groups left over
+// take repeats.
+void ising::balance_lane_chunks(uint16_t *lane_chunk, int threads) {
+  std::vector<int> cls[4];
+  for (int o = 0; o < threads; ++o) cls[__builtin_popcount(unsigned(o)) & 3].push_back(o);
+  size_t next[4] = {0, 0, 0, 0};
+  auto left = [&](int c) { return cls[c].size() - next[c]; };
+  for (int h = 0; h < threads / 32; ++h)
+    for (int g = 0; g < 8; ++g) {
+      bool used[4] = {false, false, false, false};
+      for (int j = 0; j < 4; ++j) {
+        int best = -1;
+        for (int pass = 0; pass < 2 && best < 0; ++pass)
+          for (int c = 0; c < 4; ++c)
+            if (left(c) > 0 && (pass == 1 || !used[c]) && (best < 0 || left(c) > left(best))) best = c;
+        used[best] = true;
+        lane_chunk[h * 32 + g + 8 * j] = (uint16_t)cls[best][next[best]++];
+      }
+    }
+}
+
 extern "C" ising_status ising_plan_create(const ising_lattice *lat, const ising_tune *tune,
                                           ising_plan **out) {
   return ising::plan_create_internal(lat, tune, 1, out);
@@ -173,11 +200,16 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
   // Row stride: the least even W >= n + 1.  With 16 copies a bin's bank on
   // the 32-bank LDS is 16 * (bin mod 2) + copy, and bin mod 2 = n_up mod 2
   // for even W, so lanes l and l + 16 (n_up one apart) never collide.
-  const int W = (n + 2) & ~1;
+  int W = (n + 2) & ~1;
 
   // ---- histogram replicas that fit the LDS ----
   int R = tn.replicas ? tn.replicas : 16;
   while (R > 1 && n_ec * W * R * 4 > kHistBytes) R >>= 1;
+  // With 8 copies a bin's bank is 8 * (bin mod 4) + copy: a stride that is a
+  // multiple of 4 makes bin mod 4 = n_up mod 4, and the thread -> chunk
+  // permutation (balance_lane_chunks) gives the four lanes of a half-wave
+  // that share a copy four different n_up mod 4.
+  if (R == 8 && n_ec * ((n + 4) & ~3) * R * 4 <= kHistBytes) W = (n + 4) & ~3;
   if (n_ec * W * R * 4 > kHistBytes)
     return fail(ISING_ERANGE, "compact histogram of " + std::to_string(n_ec) + " x " + std::to_string(W) +
                                   " bins exceeds the 160 KB LDS");
@@ -252,7 +284,8 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
   for (int t = 0; t < TJ; ++t) { p->site_of_bit[bit++] = tile[t]; used[tile[t]] = 1; }
   for (int s : order)
     if (!used[s]) { p->site_of_bit[bit++] = s; used[s] = 1; }
-  if (estep % 4 == 2 && n - k >= 6 && R >= 2) place_lane_spins(n, k, R, J, p->site_of_bit);
+  const bool balanced = R == 8 && W % 4 == 0;   // lanes sharing a copy never share a bin
+  if (estep % 4 == 2 && n - k >= 6 && R >= 2 && !balanced) place_lane_spins(n, k, R, J, p->site_of_bit);
   for (int b = 0; b < n; ++b) p->bit_of_site[p->site_of_bit[b]] = b;
 
   p->n_spins = n;
@@ -301,6 +334,8 @@ ising_status ising::plan_create_internal(const ising_lattice *lat, const ising_t
       // tile spin i's up-flip delta, in bytes, changes by this when bit m goes up
       d.kmid[m - TJ][i] = (int32_t)((-4 * v / estep) * row_bytes);
     }
+  for (int i = 0; i < kMaxBlockThreads; ++i) d.lane_chunk[i] = (uint16_t)i;
+  if (balanced) balance_lane_chunks(d.lane_chunk, kWave * wpb);
   p->bond = bond_plan_create(p, lat, J, classes);
   if (!p->bond) {
     delete p;
