@@ -4,7 +4,9 @@
 //
 // Grouping the configurations of Eq. (2) by (E, M):
 //   Z(T, h) = sum_{E,M} g(E, M) exp(-(E - h M)/T),  H = E - h M (Eq. (1)).
-// One block per (T, h) point:
+// One block per few temperatures (and, for one table, a group of up to 4
+// fields): the table's nonzero bins are staged in LDS as (ln g, E, M), then
+// for each temperature and group of up to 4 fields, per point:
 //   pass 1  m = max over nonzero bins of a = ln g - (E - h M)/T;
 //   pass 2  Z' = sum exp(a - m), and the weighted sums of E and M;
 //   pass 3  centred sums of (H - <H>)^2, (M - <M>)^2 and (H - <H>)(M - <M>);
@@ -44,26 +46,46 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Block-wide sums of up to 3 values; every thread gets the totals.
-__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh) {
+// Block-wide sums of N values; every thread gets the totals.  sh holds N
+// doubles per wave.  Fixed order: wave shuffles, then waves in order.
+template <int N>
+__device__ __forceinline__ void block_sums(double (&v)[N], double *sh) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
   __syncthreads();
-  if (lane == 0) { sh[wv] = a; sh[8 + wv] = b; sh[16 + wv] = c; }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) sh[wv * N + j] = v[j];
+  }
   __syncthreads();
-  a = b = c = 0.0;
-  for (int w = 0; w < nw; ++w) { a += sh[w]; b += sh[8 + w]; c += sh[16 + w]; }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += sh[w * N + j];
+    v[j] = t;
+  }
+  __syncthreads();
 }
 
-__device__ __forceinline__ double block_max(double v, double *sh) {
+template <int N>
+__device__ __forceinline__ void block_maxes(double (&v)[N], double *sh) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_max(v);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = wave_max(v[j]);
   __syncthreads();
-  if (lane == 0) sh[wv] = v;
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) sh[wv * N + j] = v[j];
+  }
   __syncthreads();
-  v = -INFINITY;
-  for (int w = 0; w < nw; ++w) v = fmax(v, sh[w]);
-  return v;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double t = -INFINITY;
+    for (int w = 0; w < nw; ++w) t = fmax(t, sh[w * N + j]);
+    v[j] = t;
+  }
+  __syncthreads();
 }
 
 // Output arrays of the FP64 evaluation; any may be NULL.
@@ -72,134 +94,276 @@ struct ThermoOut {
   double *d_T, *d_h, *d_TT, *d_Th, *d_hh;         // derivatives of log Z
 };
 
-// All outputs of one (T, h) point of one table, written at index pt.
-__device__ void thermo_point(const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
-                             double T, double h, int pt, const ThermoOut &o, double *sh) {
-  const int bins = n_e * n_m;
-  const bool want_second = o.heat || o.susc || o.d_TT || o.d_Th || o.d_hh;
-  double *const all[10] = {o.logz, o.mean_E, o.mean_M, o.heat, o.susc, o.d_T, o.d_h, o.d_TT, o.d_Th, o.d_hh};
-  if (!(T > 0.0) || !isfinite(T) || !isfinite(h)) {
-    if (threadIdx.x == 0)
-      for (int i = 0; i < 10; ++i)
-        if (all[i]) all[i][pt] = NAN;
-    return;
-  }
-  const double inv_T = 1.0 / T;
+constexpr int kHPerBlock = 4;   // field values one block evaluates at one temperature
+constexpr int kStageBins = 4096;  // nonzero bins a block keeps in LDS as (ln g, E, M)
 
-  // pass 1: the largest exponent
-  double m = -INFINITY;
+// Bins of a dense table, read in place: zero bins are skipped, ln g computed.
+struct DenseBins {
+  const unsigned long long *g;
+  int n_m, e_min, n_spins, bins;
+  __device__ int count() const { return bins; }
+  __device__ bool get(int i, double &lg, double &E, double &M) const {
+    const unsigned long long v = g[i];
+    if (!v) return false;
+    const int e = i / n_m, nu = i - e * n_m;
+    E = double(e + e_min);
+    M = double(2 * nu - n_spins);
+    lg = log(double(v));
+    return true;
+  }
+};
+
+// Nonzero bins staged in LDS (stage_bins): every entry is a real bin.
+struct StagedBins {
+  const double *lg;
+  const int *E, *M;
+  int n;
+  __device__ int count() const { return n; }
+  __device__ bool get(int i, double &l, double &e, double &m) const {
+    l = lg[i];
+    e = double(E[i]);
+    m = double(M[i]);
+    return true;
+  }
+};
+
+// Copy the nonzero bins of a dense table into LDS as (ln g, E, M), thread by
+// thread in a fixed order.  Returns their number, or -1 (every thread) when
+// more than kStageBins.  scan: blockDim.x + 1 ints of LDS.
+__device__ int stage_bins(const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
+                          double *lg, int *E, int *M, int *scan) {
+  const int bins = n_e * n_m;
+  int mine = 0;
+  for (int i = threadIdx.x; i < bins; i += blockDim.x) mine += g[i] != 0ull;
+  scan[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < int(blockDim.x); ++t) {
+      const int c = scan[t];
+      scan[t] = run;
+      run += c;
+    }
+    scan[blockDim.x] = run;
+  }
+  __syncthreads();
+  const int total = scan[blockDim.x];
+  if (total > kStageBins) return -1;
+  int at = scan[threadIdx.x];
   for (int i = threadIdx.x; i < bins; i += blockDim.x) {
     const unsigned long long v = g[i];
     if (!v) continue;
     const int e = i / n_m, nu = i - e * n_m;
-    const double E = double(e + e_min), M = double(2 * nu - n_spins);
-    m = fmax(m, log(double(v)) - (E - h * M) * inv_T);
+    lg[at] = log(double(v));
+    E[at] = e + e_min;
+    M[at] = 2 * nu - n_spins;
+    ++at;
   }
-  m = block_max(m, sh);
-  if (m == -INFINITY) {   // empty table: Z = 0
-    if (threadIdx.x == 0) {
+  __syncthreads();
+  return total;
+}
+
+// All outputs at temperature T and the fields h[0 .. cnt) (cnt <= kHPerBlock)
+// of one table, written at indices pt0 + j.  Each bin is read once per pass
+// for all cnt points.
+template <class Bins>
+__device__ void thermo_points(const Bins &B, double T, const double *__restrict__ h, int cnt, int pt0,
+                              const ThermoOut &o, double *sh) {
+  constexpr int P = kHPerBlock;
+  const int bins = B.count();
+  const bool want_second = o.heat || o.susc || o.d_TT || o.d_Th || o.d_hh;
+  double *const all[10] = {o.logz, o.mean_E, o.mean_M, o.heat, o.susc, o.d_T, o.d_h, o.d_TT, o.d_Th, o.d_hh};
+  double hv[P];
+  bool ok[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    hv[j] = j < cnt ? h[j] : 0.0;
+    ok[j] = j < cnt && (T > 0.0) && isfinite(T) && isfinite(hv[j]);
+    if (!ok[j]) hv[j] = 0.0;
+  }
+  const double inv_T = (T > 0.0 && isfinite(T)) ? 1.0 / T : 0.0;
+
+  // pass 1: the largest exponent per point
+  double m[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) m[j] = -INFINITY;
+  for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+    double lg, E, M;
+    if (!B.get(i, lg, E, M)) continue;
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (j < cnt) m[j] = fmax(m[j], lg - (E - hv[j] * M) * inv_T);
+  }
+  block_maxes(m, sh);
+#pragma unroll
+  for (int j = cnt; j < P; ++j) m[j] = m[0];
+
+  // pass 2: Z' and first moments
+  double acc[3 * P];
+#pragma unroll
+  for (int j = 0; j < 3 * P; ++j) acc[j] = 0.0;
+  if (m[0] != -INFINITY) {   // all points see the same nonzero bins
+    for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+      double lg, E, M;
+      if (!B.get(i, lg, E, M)) continue;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (j >= cnt) break;
+        const double w = exp(lg - (E - hv[j] * M) * inv_T - m[j]);
+        acc[3 * j] += w;
+        acc[3 * j + 1] += w * E;
+        acc[3 * j + 2] += w * M;
+      }
+    }
+  }
+  block_sums(acc, sh);
+  double mE[P], mM[P], z[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    z[j] = acc[3 * j];
+    mE[j] = acc[3 * j + 1] / z[j];
+    mM[j] = acc[3 * j + 2] / z[j];
+  }
+
+  // pass 3: centred second moments of H = E - hM and M
+  if (want_second && m[0] != -INFINITY) {
+#pragma unroll
+    for (int j = 0; j < 3 * P; ++j) acc[j] = 0.0;
+    for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+      double lg, E, M;
+      if (!B.get(i, lg, E, M)) continue;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (j >= cnt) break;
+        const double w = exp(lg - (E - hv[j] * M) * inv_T - m[j]);
+        const double dH = (E - hv[j] * M) - (mE[j] - hv[j] * mM[j]), dM = M - mM[j];
+        acc[3 * j] += w * dH * dH;
+        acc[3 * j + 1] += w * dM * dM;
+        acc[3 * j + 2] += w * dH * dM;
+      }
+    }
+    block_sums(acc, sh);
+  }
+
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (j >= cnt) break;
+    const int pt = pt0 + j;
+    if (!ok[j]) {
+#pragma unroll
+      for (int i = 0; i < 10; ++i)
+        if (all[i]) all[i][pt] = NAN;
+      continue;
+    }
+    if (m[j] == -INFINITY) {   // empty table: Z = 0
+#pragma unroll
       for (int i = 1; i < 10; ++i)
         if (all[i]) all[i][pt] = NAN;
       if (o.logz) o.logz[pt] = -INFINITY;
+      continue;
     }
-    return;
-  }
-
-  // pass 2: Z' and first moments
-  double z = 0.0, se = 0.0, sm = 0.0;
-  for (int i = threadIdx.x; i < bins; i += blockDim.x) {
-    const unsigned long long v = g[i];
-    if (!v) continue;
-    const int e = i / n_m, nu = i - e * n_m;
-    const double E = double(e + e_min), M = double(2 * nu - n_spins);
-    const double w = exp(log(double(v)) - (E - h * M) * inv_T - m);
-    z += w;
-    se += w * E;
-    sm += w * M;
-  }
-  block_sum3(z, se, sm, sh);
-  const double mE = se / z, mM = sm / z;
-  const double mH = mE - h * mM;
-  if (threadIdx.x == 0) {
-    if (o.logz) o.logz[pt] = m + log(z);
-    if (o.mean_E) o.mean_E[pt] = mE;
-    if (o.mean_M) o.mean_M[pt] = mM;
-    if (o.d_T) o.d_T[pt] = mH * inv_T * inv_T;
-    if (o.d_h) o.d_h[pt] = mM * inv_T;
-  }
-  if (!want_second) return;
-
-  // pass 3: centred second moments of H = E - hM and M
-  double vh = 0.0, vm = 0.0, chm = 0.0;
-  for (int i = threadIdx.x; i < bins; i += blockDim.x) {
-    const unsigned long long v = g[i];
-    if (!v) continue;
-    const int e = i / n_m, nu = i - e * n_m;
-    const double E = double(e + e_min), M = double(2 * nu - n_spins);
-    const double w = exp(log(double(v)) - (E - h * M) * inv_T - m);
-    const double dH = (E - h * M) - mH, dM = M - mM;
-    vh += w * dH * dH;
-    vm += w * dM * dM;
-    chm += w * dH * dM;
-  }
-  block_sum3(vh, vm, chm, sh);
-  if (threadIdx.x == 0) {
-    const double varH = vh / z, varM = vm / z, cov = chm / z;
-    const double T2 = inv_T * inv_T;
-    if (o.heat) o.heat[pt] = varH * T2;
-    if (o.susc) o.susc[pt] = varM * inv_T;
-    if (o.d_TT) o.d_TT[pt] = varH * T2 * T2 - 2.0 * mH * T2 * inv_T;
-    if (o.d_Th) o.d_Th[pt] = (cov * inv_T - mM) * T2;
-    if (o.d_hh) o.d_hh[pt] = varM * T2;
+    const double mH = mE[j] - hv[j] * mM[j], T2 = inv_T * inv_T;
+    if (o.logz) o.logz[pt] = m[j] + log(z[j]);
+    if (o.mean_E) o.mean_E[pt] = mE[j];
+    if (o.mean_M) o.mean_M[pt] = mM[j];
+    if (o.d_T) o.d_T[pt] = mH * T2;
+    if (o.d_h) o.d_h[pt] = mM[j] * inv_T;
+    if (want_second) {
+      const double varH = acc[3 * j] / z[j], varM = acc[3 * j + 1] / z[j], cov = acc[3 * j + 2] / z[j];
+      if (o.heat) o.heat[pt] = varH * T2;
+      if (o.susc) o.susc[pt] = varM * inv_T;
+      if (o.d_TT) o.d_TT[pt] = varH * T2 * T2 - 2.0 * mH * T2 * inv_T;
+      if (o.d_Th) o.d_Th[pt] = (cov * inv_T - mM[j]) * T2;
+      if (o.d_hh) o.d_hh[pt] = varM * T2;
+    }
   }
 }
+
+// A block's table: its nonzero bins are staged in LDS once (ln g taken once
+// per bin), then every lane of every pass works on a real bin; tables with
+// more nonzero bins than fit are read in place.
+constexpr int kTPerBlock = 8;   // temperatures per block of the batched kernel
+
+struct StageLds {
+  double lg[kStageBins];
+  int E[kStageBins], M[kStageBins];
+  int scan[kThermoThreads + 1];
+  double sh[(kThermoThreads / 64) * 3 * kHPerBlock];
+};
+
+// Temperatures [a0, a1) x field groups [c_lo, c_hi) (in units of
+// kHPerBlock) of one table.
+__device__ void thermo_block(const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
+                             const double *__restrict__ Tg, int a0, int a1, const double *__restrict__ hg, int nh,
+                             int c_lo, int c_hi, int out_base, const ThermoOut &o, StageLds &L) {
+  const int staged = stage_bins(g, n_e, n_m, e_min, n_spins, L.lg, L.E, L.M, L.scan);
+  for (int a = a0; a < a1; ++a)
+    for (int cg = c_lo; cg < c_hi; ++cg) {
+      const int c0 = cg * kHPerBlock;
+      const int cnt = min(kHPerBlock, nh - c0), pt0 = out_base + a * nh + c0;
+      if (staged >= 0)
+        thermo_points(StagedBins{L.lg, L.E, L.M, staged}, Tg[a], hg + c0, cnt, pt0, o, L.sh);
+      else
+        thermo_points(DenseBins{g, n_m, e_min, n_spins, n_e * n_m}, Tg[a], hg + c0, cnt, pt0, o, L.sh);
+    }
+}
+
+// One table: grid (ceil(nT / kTSingle), ceil(nh / kHPerBlock)); block (x, y)
+// covers kTSingle temperatures and one field group; outputs [nT][nh].
+constexpr int kTSingle = 2;
 
 __global__ __launch_bounds__(kThermoThreads) void k_thermo(
     const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
     const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh, ThermoOut o) {
-  __shared__ double sh[24];
-  const int pt = blockIdx.x;
-  const int ia = pt / nh, ib = pt - ia * nh;
-  thermo_point(g, n_e, n_m, e_min, n_spins, Tg[ia], hg[ib], pt, o, sh);
+  __shared__ StageLds L;
+  const int a0 = blockIdx.x * kTSingle, a1 = min(nT, a0 + kTSingle);
+  thermo_block(g, n_e, n_m, e_min, n_spins, Tg, a0, a1, hg, nh, blockIdx.y, blockIdx.y + 1, 0, o, L);
 }
 
-// One thread per dense bin; the (T, h) points are summed in a fixed order.
+// One thread block per dense bin; its threads split the (T, h) points and the
+// partial sums meet in a fixed-order block reduction.
 __global__ __launch_bounds__(256) void k_bin_weights(
     const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
     const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
     const double *__restrict__ logz, const double *__restrict__ G, double *__restrict__ W) {
+  __shared__ double sh[256 / 64];
   const int bins = n_e * n_m;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < bins; i += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    if (g[i]) {
-      const int e = i / n_m, nu = i - e * n_m;
-      const double E = double(e + e_min), M = double(2 * nu - n_spins);
-      for (int a = 0; a < nT; ++a) {
-        const double inv_T = 1.0 / Tg[a];
-        for (int c = 0; c < nh; ++c) {
-          const double gc = G[a * nh + c];
-          if (gc != 0.0) acc += gc * exp(-(E - hg[c] * M) * inv_T - logz[a * nh + c]) * inv_T;
-        }
-      }
+  for (int i = blockIdx.x; i < bins; i += gridDim.x) {
+    if (!g[i]) {   // uniform over the block
+      if (threadIdx.x == 0) W[i] = 0.0;
+      continue;
     }
-    W[i] = acc;
+    const int e = i / n_m, nu = i - e * n_m;
+    const double E = double(e + e_min), M = double(2 * nu - n_spins);
+    double acc = 0.0;
+    for (int pt = threadIdx.x; pt < nT * nh; pt += blockDim.x) {
+      const double gc = G[pt];
+      if (gc == 0.0) continue;
+      const int a = pt / nh, c = pt - a * nh;
+      const double inv_T = 1.0 / Tg[a];
+      acc += gc * exp(-(E - hg[c] * M) * inv_T - logz[pt]) * inv_T;
+    }
+    double one[1] = {acc};
+    block_sums(one, sh);
+    if (threadIdx.x == 0) W[i] = one[0];
   }
 }
 
-// Batched: block (pt, member) evaluates point pt of member `member`; outputs
-// are [member][nT][nh].
+// Batched: grid (ceil(nT / kTPerBlock), members); block (x, member) covers
+// kTPerBlock temperatures and every field; outputs [member][nT][nh].
 __global__ __launch_bounds__(kThermoThreads) void k_batch_thermo(
     const unsigned long long *__restrict__ g_all, const BatchMember *__restrict__ meta,
     const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
     double *__restrict__ logz, double *__restrict__ mean_E, double *__restrict__ mean_M,
     double *__restrict__ heat, double *__restrict__ susc) {
-  __shared__ double sh[24];
-  const int pt = blockIdx.x, member = blockIdx.y;
-  const int ia = pt / nh, ib = pt - ia * nh;
+  __shared__ StageLds L;
+  const int member = blockIdx.y;
   const BatchMember mb = meta[member];
-  const int out = member * nT * nh + pt;
   const ThermoOut o{logz, mean_E, mean_M, heat, susc, nullptr, nullptr, nullptr, nullptr, nullptr};
-  thermo_point(g_all + mb.offset, mb.n_e, mb.n_m, mb.e_min, mb.n_spins, Tg[ia], hg[ib], out, o, sh);
+  const int a0 = blockIdx.x * kTPerBlock, a1 = min(nT, a0 + kTPerBlock);
+  thermo_block(g_all + mb.offset, mb.n_e, mb.n_m, mb.e_min, mb.n_spins, Tg, a0, a1, hg, nh, 0,
+               (nh + kHPerBlock - 1) / kHPerBlock, member * nT * nh, o, L);
 }
 
 ising_status batch_thermo_launch(const BatchMember *meta_dev, int n_members, const uint64_t *g_all,
@@ -207,10 +371,11 @@ ising_status batch_thermo_launch(const BatchMember *meta_dev, int n_members, con
                                  double *mE, double *mM, double *C, double *chi, hipStream_t stream) {
   if (nT == 0 || nh == 0 || n_members == 0) return ISING_OK;
   if (!T_dev || !h_dev) return fail(ISING_EINVAL, "T_dev or h_dev is NULL");
-  if (int64_t(nT) * nh > 65535 * 64) return fail(ISING_EINVAL, "grid too large");
-  hipLaunchKernelGGL(k_batch_thermo, dim3(unsigned(nT * nh), unsigned(n_members)), dim3(kThermoThreads), 0, stream,
-                     reinterpret_cast<const unsigned long long *>(g_all), meta_dev, T_dev, nT, h_dev, nh, logz, mE,
-                     mM, C, chi);
+  if (int64_t(nT) * nh > (int64_t(1) << 30) || n_members > 65535) return fail(ISING_EINVAL, "grid too large");
+  hipLaunchKernelGGL(k_batch_thermo, dim3(unsigned((nT + kTPerBlock - 1) / kTPerBlock), unsigned(n_members)),
+                     dim3(kThermoThreads), 0,
+                     stream, reinterpret_cast<const unsigned long long *>(g_all), meta_dev, T_dev, nT, h_dev, nh,
+                     logz, mE, mM, C, chi);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_batch_thermo launch: ") + hipGetErrorString(e));
   return ISING_OK;
@@ -234,7 +399,9 @@ static ising_status thermo_launch(const uint64_t *g_dev, int32_t n_e, int32_t n_
   if (st != ISING_OK) return st;
   if (nT == 0 || nh == 0) return ISING_OK;
   if (!T_dev || !h_dev) return fail(ISING_EINVAL, "T_dev or h_dev is NULL");
-  hipLaunchKernelGGL(k_thermo, dim3(unsigned(nT * nh)), dim3(kThermoThreads), 0, static_cast<hipStream_t>(stream),
+  const dim3 grid(unsigned((nT + kTSingle - 1) / kTSingle), unsigned((nh + kHPerBlock - 1) / kHPerBlock));
+  if (grid.y > 65535) return fail(ISING_EINVAL, "too many field values");
+  hipLaunchKernelGGL(k_thermo, grid, dim3(kThermoThreads), 0, static_cast<hipStream_t>(stream),
                      reinterpret_cast<const unsigned long long *>(g_dev), n_e, n_m, e_min, n_spins, T_dev, nT,
                      h_dev, nh, o);
   hipError_t e = hipGetLastError();
@@ -282,7 +449,7 @@ extern "C" ising_status ising_bin_weights(const uint64_t *g_dev, int32_t n_e, in
   if (nT > 0 && nh > 0 && (!T_dev || !h_dev || !logz_dev || !grad_dev))
     return fail(ISING_EINVAL, "T_dev, h_dev, logz_dev or grad_dev is NULL");
   const int bins = n_e * n_m;
-  const int blocks = std::min((bins + 255) / 256, 4096);
+  const int blocks = std::min(bins, 65536);
   hipLaunchKernelGGL(k_bin_weights, dim3(unsigned(blocks)), dim3(256), 0, static_cast<hipStream_t>(stream),
                      reinterpret_cast<const unsigned long long *>(g_dev), n_e, n_m, e_min, n_spins, T_dev,
                      nT > 0 && nh > 0 ? nT : 0, h_dev, nT > 0 && nh > 0 ? nh : 0, logz_dev, grad_dev, W_dev);
