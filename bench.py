@@ -35,17 +35,18 @@ INT_VALU_PEAK = 256 * 64 * 2.4e9
 # hold only for the kernel sources they were taken on: if the sources' hash
 # differs, the figures are reported as null.
 COUNTERS = {
-    "sources": ["paper_1110_2561_amd/csrc/enumerate.hip", "paper_1110_2561_amd/csrc/plan.cpp",
-                "paper_1110_2561_amd/csrc/internal.h"],
-    "sha256": "8382edbec6341ebe8163d8be8cb3c23846226af73bb425cb77bdb436a112b666",
+    # rocprofv3 counters of k_enumerate on the 6x6 torus (profiles/k_enumerate_torus6x6_*.txt),
+    # valid while the kernel's sources hash to sha256.
+    "sources": ['paper_1110_2561_amd/csrc/enumerate.hip', 'paper_1110_2561_amd/csrc/walk.h', 'paper_1110_2561_amd/csrc/plan.cpp', 'paper_1110_2561_amd/csrc/internal.h'],
+    "sha256": "0684bdfbe1b9ca1900f3d9cc53c9419c4e16c0ed6f8aa3dffcc4e5f76313d1a0",
     "workload": "torus6x6",
-    # FETCH_SIZE 64.5 KiB x 2.0 + WRITE_SIZE 896.1 KiB x 1.0 per launch; the
+    # FETCH_SIZE 81.0 KiB x 2.0 + WRITE_SIZE 936.28 KiB x 1.0 per launch; the
     # factors are what a 512 MiB copy kernel reads on the same counters.
-    "hbm_bytes_per_launch": int((64.5 * 2.0 + 896.09375 * 1.0) * 1024),
+    "hbm_bytes_per_launch": int((81.0 * 2.0 + 936.28125 * 1.0) * 1024),
     # SQ_INSTS_VALU_INT32 x 64 lanes / 2^36 configurations
-    "int32_valu_per_config": 1145449772 * 64 / 2 ** 36,
+    "int32_valu_per_config": 1132903146 * 64 / 2 ** 36,
     # SQ_INSTS_VALU x 64 lanes / 2^36 configurations (all VALU)
-    "valu_per_config": 1236714060 * 64 / 2 ** 36,
+    "valu_per_config": 1210544730 * 64 / 2 ** 36,
 }
 
 
