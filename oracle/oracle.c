@@ -64,18 +64,23 @@ static void *count_worker(void *arg) {
 }
 
 /* Count configurations with index in [first, first + count) into g (added,
- * not overwritten).  Returns 0 on success, <0 on bad arguments. */
+ * not overwritten).  Returns 0 on success, <0 on bad arguments.  For n = 64
+ * the range must end before the last configuration (indices are uint64). */
 int oracle_count_range(int n, int nb, const int32_t *bi, const int32_t *bj,
                        const int32_t *bJ, uint64_t first, uint64_t count,
                        int n_threads, uint64_t *g) {
-  if (n < 1 || n > 62 || nb < 0 || n_threads < 1 || !g) return -1;
+  if (n < 1 || n > 64 || nb < 0 || n_threads < 1 || !g) return -1;
   int64_t S = 0;
   for (int b = 0; b < nb; ++b) {
     if (bi[b] < 0 || bi[b] >= n || bj[b] < 0 || bj[b] >= n) return -2;
     S += bJ[b] < 0 ? -(int64_t)bJ[b] : bJ[b];
   }
-  const uint64_t total = (uint64_t)1 << n;
-  if (first > total || count > total - first) return -3;
+  if (n < 64) {
+    const uint64_t total = (uint64_t)1 << n;
+    if (first > total || count > total - first) return -3;
+  } else if (count > UINT64_MAX - first) {
+    return -3;
+  }
   const size_t cells = (size_t)(2 * S + 1) * (size_t)(n + 1);
   if (count == 0) return 0;
   if ((uint64_t)n_threads > count) n_threads = (int)count;

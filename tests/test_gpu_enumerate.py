@@ -134,12 +134,22 @@ def test_ranges_sum_to_whole(api):
     assert torch.equal(whole.cpu(), parts.cpu())
 
 
-@pytest.mark.parametrize("name", ["torus6x6", "torus8x5_pm"])
+LARGE = {
+    "torus6x6": L.workload("torus6x6")["lattice"],
+    "torus8x5_pm": L.workload("torus8x5_pm")["lattice"],
+    "torus8x8_pm": L.square_torus(8, 8, L.pm_couplings(128, 64)),                      # N = 64, 8 copies
+    "random50": L.random_bond_lattice(50, 120, 50, values=(-2, -1, 1, 2)),           # 4 copies
+    "cubic4": L.cubic_torus(4, L.choice_couplings(192, 4)),                           # N = 64, 6 neighbours
+}
+
+
+@pytest.mark.parametrize("name", list(LARGE))
 def test_sampled_range_vs_bruteforce(api, name):
     """Full-size plan, a sampled chunk range: the same configurations counted
     by the brute force after renaming sites to the plan's bit positions."""
-    lat = L.workload(name)["lattice"]
+    lat = LARGE[name]
     plan = api.Plan(lat)
+    print(f"{name}: N={lat.n_spins} inner={plan.inner_bits} tile={plan.tile_bits} chunks={plan.n_chunks}", flush=True)
     k = plan.inner_bits
     n_ch = max(1, (1 << 26) >> k)
     rng = np.random.default_rng(1234)
