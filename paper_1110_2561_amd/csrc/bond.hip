@@ -12,12 +12,13 @@
 //   * the tile walk (2^TJ configurations, only tile bits flip, fully
 //     unrolled) reads W of each configuration from an LDS copy of the table
 //     (one ds_read_b64 on the same running address as the forward's
-//     histogram add) and keeps its running sum sw.  The sum of W over the
-//     configurations with tile spin i up is collected by a prefix-sum trick:
-//     when spin i goes up remember sw, when it goes down add sw minus the
-//     remembered value.  Which spin flips, and which way, is a compile-time
-//     fact of the unrolled Gray sequence, so a step costs one load, one add
-//     and one add or copy.
+//     histogram add).  The sums of W over the configurations with tile spin
+//     i up come from groups of 8 configurations: an add tree of the group
+//     gives tile bits 0-2 (up on fixed positions of the group), and higher
+//     tile bits, which flip only between groups, use a prefix-sum trick on
+//     the running sum of group totals.  Which spin flips, and which way, is a
+//     compile-time fact of the unrolled Gray sequence, so a configuration
+//     costs one load, one integer add and about two FP64 adds.
 //   * per tile block (walk) q the sums S_q = sum W and Y_q,i = sum W s_i are
 //     folded into chunk totals: sum W, sum W s_t, sum W s_m, sum W s_t s_m,
 //     sum W s_m1 s_m2 (s_m, the middle spins, are fixed within a block).
@@ -63,55 +64,102 @@ __host__ __device__ constexpr uint32_t tile_state(int t) {
   return uint32_t(t ^ (t >> 1)) ^ (ODD ? (1u << (TJ - 1)) : 0u);
 }
 
+// Tile blocks of TJ >= 3 bits, in groups of 8 configurations (the low three
+// tile bits): inside a group, tile bits 0-2 are up on fixed position sets
+// ({1,2,5,6}, {2,3,4,5}, {4..7} or {0..3}, or their complements for the top
+// bit of an odd block), so their sums come from a small add tree of the
+// group (pairs, quads, total); higher tile bits flip only between groups and
+// use the prefix-sum trick on the running sum of group totals (subtract it
+// when the spin goes up, add it when it goes down, add the total at the end
+// if still up).  About two FP64 adds per configuration, with a dependent
+// chain of one add per group instead of one per configuration.
+template <int TJ, bool ODD>
+__device__ __forceinline__ double group_bit_sum(int g, int b, const double (&w)[8], double P23, double P45,
+                                                double Q0, double Q1, double G) {
+  uint32_t mask = 0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) mask |= ((tile_state<TJ, ODD>(8 * g + u) >> b) & 1u) << u;
+  switch (mask) {
+    case 0x66: return (w[1] + w[2]) + (w[5] + w[6]);
+    case 0x99: return G - ((w[1] + w[2]) + (w[5] + w[6]));
+    case 0x3c: return P23 + P45;
+    case 0xc3: return G - (P23 + P45);
+    case 0xf0: return Q1;
+    case 0x0f: return Q0;
+    default: {   // not reached for the reflected Gray code; kept general
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if ((mask >> u) & 1u) acc += w[u];
+      return acc;
+    }
+  }
+}
+
 template <int TJ, bool ODD>
 __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ], const char *wt, double &sw,
                                             double (&U)[TJ]) {
   constexpr int kN = 1 << TJ;
-  constexpr int kG = kN < 8 ? kN : 8;   // configurations per load group
-  constexpr int kGroups = kN / kG;
   constexpr uint32_t kEnd = tile_state<TJ, ODD>(kN - 1);
-  double L[TJ];   // running sum before the configuration where spin i last went up
 #pragma unroll
-  for (int i = 0; i < TJ; ++i) {
-    U[i] = 0.0;
-    L[i] = 0.0;
-  }
+  for (int i = 0; i < TJ; ++i) U[i] = 0.0;
   sw = 0.0;
-  // W of configuration t is loaded one group ahead of its use, so the LDS
-  // latency of a group overlaps the sums of the previous one.
-  double w[2][kG];
+  if constexpr (TJ >= 3) {
+    constexpr int kGroups = kN / 8;
+    // W of a group is loaded one group ahead of its sums.
+    double w[2][8];
 #pragma unroll
-  for (int g = 0; g <= kGroups; ++g) {
-    if (g < kGroups) {
+    for (int g = 0; g <= kGroups; ++g) {
+      if (g < kGroups) {
 #pragma unroll
-      for (int u = 0; u < kG; ++u) {
-        const int t = g * kG + u;
-        if (t > 0) {
-          const int b = __builtin_ctz(t);
-          A = ((tile_state<TJ, ODD>(t) >> b) & 1u) ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
+        for (int u = 0; u < 8; ++u) {
+          const int t = g * 8 + u;
+          if (t > 0) {
+            const int b = __builtin_ctz(t);
+            A = ((tile_state<TJ, ODD>(t) >> b) & 1u) ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
+          }
+          w[g & 1][u] = lds_f64(wt, A);
         }
-        w[g & 1][u] = lds_f64(wt, A);
       }
-    }
-    if (g > 0) {
-      const int gp = g - 1;
-#pragma unroll
-      for (int u = 0; u < kG; ++u) {
-        const int t = gp * kG + u;
-        if (t > 0) {   // spin b flipped on entering configuration t
-          const int b = __builtin_ctz(t);
-          if ((tile_state<TJ, ODD>(t) >> b) & 1u)
-            L[b] = sw;
+      if (g > 0) {
+        const int gp = g - 1;
+        const double(&v)[8] = w[gp & 1];
+        if (gp > 0) {   // a tile bit >= 3 flipped on entering this group
+          const int b = __builtin_ctz(gp * 8);
+          if ((tile_state<TJ, ODD>(gp * 8) >> b) & 1u)
+            U[b] -= sw;
           else
-            U[b] += sw - L[b];
+            U[b] += sw;
         }
-        sw += w[gp & 1][u];
+        const double P01 = v[0] + v[1], P23 = v[2] + v[3], P45 = v[4] + v[5], P67 = v[6] + v[7];
+        const double Q0 = P01 + P23, Q1 = P45 + P67, G = Q0 + Q1;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) U[b] += group_bit_sum<TJ, ODD>(gp, b, v, P23, P45, Q0, Q1, G);
+        sw += G;
       }
     }
-  }
 #pragma unroll
-  for (int i = 0; i < TJ; ++i)
-    if ((kEnd >> i) & 1u) U[i] += sw - L[i];
+    for (int i = 3; i < TJ; ++i)
+      if ((kEnd >> i) & 1u) U[i] += sw;
+  } else {
+    // one or two tile bits: the prefix-sum trick per configuration
+#pragma unroll
+    for (int t = 0; t < kN; ++t) {
+      if (t > 0) {
+        const int b = __builtin_ctz(t);
+        const bool up = ((tile_state<TJ, ODD>(t) >> b) & 1u) != 0;
+        A = up ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
+        if (up)
+          U[b] -= sw;
+        else
+          U[b] += sw;
+      }
+      sw += lds_f64(wt, A);
+    }
+#pragma unroll
+    for (int i = 0; i < TJ; ++i)
+      if ((kEnd >> i) & 1u) U[i] += sw;
+  }
 }
 
 // Chunk totals of one lane (sums over the chunk's 2^k configurations).
