@@ -14,6 +14,7 @@ namespace ising {
 constexpr int kMaxPairs = 512;      // distinct bond pairs the per-bond backward handles
 constexpr int kBwMid = 4;           // middle bits of the backward walk (at most)
 constexpr int kBwWaves = 8;         // waves per block of the backward kernel
+constexpr int kMaxBwBlocks = 1024;  // blocks whose partial sums the workspace holds
 
 // Where each distinct bond pair of the lattice sits in the backward walk
 // (bit positions of the backward geometry: tile [0, TJ), middle [TJ, TJ + mj),

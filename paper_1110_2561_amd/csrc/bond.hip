@@ -49,8 +49,6 @@ namespace ising {
     if (e_ != hipSuccess) return fail(ISING_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kMaxBwBlocks = 1024;
-
 __device__ __forceinline__ double lds_f64(const char *base, uint32_t byte_addr) {
   return *reinterpret_cast<const double *>(base + byte_addr);
 }
@@ -418,13 +416,6 @@ static ising_status bond_dispatch(int tile, int n_classes, const DevPlan *dP, co
 }  // namespace ising
 
 using namespace ising;
-
-extern "C" ising_status ising_bond_workspace(const ising_plan *p, size_t *bytes) {
-  if (!p || !bytes) return fail(ISING_EINVAL, "plan or bytes is NULL");
-  if (p->bond->status != ISING_OK) return fail(p->bond->status, p->bond->error);
-  *bytes = size_t(kMaxBwBlocks) * size_t(std::max(p->bond->tables.n_pairs, 1)) * sizeof(double);
-  return ISING_OK;
-}
 
 extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev,
                                             void *workspace, size_t workspace_bytes, void *stream) {

@@ -124,3 +124,12 @@ BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const 
 }
 
 }  // namespace ising
+
+using namespace ising;
+
+extern "C" ising_status ising_bond_workspace(const ising_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(ISING_EINVAL, "plan or bytes is NULL");
+  if (p->bond->status != ISING_OK) return fail(p->bond->status, p->bond->error);
+  *bytes = size_t(kMaxBwBlocks) * size_t(std::max(p->bond->tables.n_pairs, 1)) * sizeof(double);
+  return ISING_OK;
+}

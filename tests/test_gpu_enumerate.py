@@ -134,6 +134,33 @@ def test_ranges_sum_to_whole(api):
     assert torch.equal(whole.cpu(), parts.cpu())
 
 
+def test_checkpoint_and_resume(api, tmp_path):
+    """An interrupted run resumes from a saved partial table and chunk offset:
+    a first plan enumerates a prefix of the chunk range and checkpoints
+    (table, next chunk) to disk; a fresh plan loads it and finishes."""
+    lat = L.workload("torus8x5_pm")["lattice"]
+    whole = api.enumerate_g(api.Plan(lat)).cpu().numpy()
+    plan1 = api.Plan(lat)
+    g = torch.zeros((plan1.n_e, plan1.n_m), dtype=torch.uint64, device="cuda")
+    stop = plan1.n_chunks // 3 + 11
+    step = max(1, stop // 4)
+    done = 0
+    while done < stop:                       # the first run, in pieces
+        n = min(step, stop - done)
+        api.enumerate_range(plan1, done, n, g)
+        done += n
+    torch.cuda.synchronize()
+    np.save(tmp_path / "partial.npy", g.cpu().numpy().view(np.int64))
+    (tmp_path / "next_chunk.txt").write_text(str(done))
+    del g, plan1                             # the run ends here
+    plan2 = api.Plan(lat)
+    resumed = torch.from_numpy(np.load(tmp_path / "partial.npy")).view(torch.uint64).cuda()
+    nxt = int((tmp_path / "next_chunk.txt").read_text())
+    api.enumerate_range(plan2, nxt, plan2.n_chunks - nxt, resumed)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(resumed.cpu().numpy(), whole)
+
+
 LARGE = {
     "torus6x6": L.workload("torus6x6")["lattice"],
     "torus8x5_pm": L.workload("torus8x5_pm")["lattice"],
