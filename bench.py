@@ -324,6 +324,8 @@ def main() -> int:
             "frac": COUNTERS["int32_valu_per_config"] * achieved / INT_VALU_PEAK if valid else None,
             "int32_valu_per_config": COUNTERS["int32_valu_per_config"] if valid else None,
             "basis": "rocprofv3 SQ_INSTS_VALU_INT32 x 64 lanes per configuration, times the event-timed rate",
+            "note": "about one int32 op per configuration by design: the LDS atomic unit, not the integer "
+                    "VALU, bounds the walk; narrower tiles do more integer work per configuration at a lower rate",
         },
     }
     if not args.no_extras:
