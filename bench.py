@@ -74,9 +74,28 @@ def cpu_baseline(lat, sample_log2: int) -> dict:
     t0 = time.perf_counter()
     native.count_range(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J, 0, count, threads)
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": count / dt, "unit": "configs/s", "cores": threads, "kind": "oracle",
             "sample": f"configurations [0, 2^{sample_log2}) of the {lat.n_spins}-spin workload, "
-                      f"brute force over bonds, {dt:.1f} s wall"}
+                      f"brute force over bonds, {dt:.1f} s wall",
+            "host": f"{model}; {os.cpu_count()} logical CPUs visible, {threads} threads used"}
+
+
+def gray_step_ops(lat) -> int:
+    """Integer ops of one popcount-based Gray step (a flip, then per coupling
+    class an AND + popcount-accumulate and a scale by J_c, then the sign and
+    the E/M update, then the bin update), for masks held in one 32-bit word
+    with a good site ordering: 1 + 2 n_c + n_c + 2 + 1."""
+    n_c = len({int(v) for v in lat.bond_J if int(v) != 0}) or 1
+    return 1 + 2 * n_c + n_c + 2 + 1
 
 
 def copy_calibration(nbytes: int) -> int:
@@ -326,6 +345,14 @@ def main() -> int:
             "basis": "rocprofv3 SQ_INSTS_VALU_INT32 x 64 lanes per configuration, times the event-timed rate",
             "note": "about one int32 op per configuration by design: the LDS atomic unit, not the integer "
                     "VALU, bounds the walk; narrower tiles do more integer work per configuration at a lower rate",
+            "algorithmic": {
+                "ops_per_config": gray_step_ops(lat),
+                "achieved": gray_step_ops(lat) * achieved / 1e12,
+                "frac": gray_step_ops(lat) * achieved / INT_VALU_PEAK,
+                "basis": "configs/s x the integer ops of a popcount-based Gray step (flip; AND, popcount-"
+                         "accumulate and J scale per coupling class; sign; E/M update; bin update), over "
+                         "the int32 VALU peak: the work rate the walk delivers, in integer-op equivalents",
+            },
         },
     }
     if not args.no_extras:
