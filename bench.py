@@ -134,10 +134,17 @@ def bench_batched(plain_rate: float, reps: int) -> dict:
     of {zero, enumerate, moments}; reported beside the plain kernel."""
     import torch
 
-    from paper_1110_2561_amd import api
+    from dataclasses import asdict
+
+    from paper_1110_2561_amd import api, autotune
     from paper_1110_2561_amd import lattice as L
     w = L.workload("batch256")
-    plan = api.BatchPlan(w["lattices"])
+    # chunk / tile / copy choices picked by the autotuner on this GPU (timed
+    # outside the measurement; not cached, so the line reflects this run)
+    t0 = time.perf_counter()
+    tune, tried = autotune.autotune_batch(w["lattices"], reps=2, use_cache=False)
+    tune_s = time.perf_counter() - t0
+    plan = api.BatchPlan(w["lattices"], tune)
     g = plan.new_tables()
     api.batch_enumerate(plan, out=g)
     torch.cuda.synchronize()
@@ -161,6 +168,8 @@ def bench_batched(plain_rate: float, reps: int) -> dict:
         "graph_ms": gms,
         "graph": f"zero + batched enumerate + batched moments on {len(w['T'])} T x {len(w['h'])} h",
         "vs_plain": total / (ms * 1e-3) / plain_rate,
+        "tune": {k: v for k, v in asdict(tune).items() if v},
+        "autotune": f"{len(tried)} candidate tunes timed in {tune_s:.1f} s",
     }
 
 

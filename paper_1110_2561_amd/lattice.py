@@ -234,6 +234,7 @@ def T_GRID(n: int) -> np.ndarray:
 
 
 _PM_SEED_8x5 = 20111025
+_PM_SEED_CUBE = 27
 _BATCH_SEED = 1110_2561
 
 
@@ -255,7 +256,8 @@ def workload(name: str) -> dict:
         return {"lattices": batch_lattices(256, _BATCH_SEED), "T": T_GRID(64),
                 "h": np.array([0.0, 0.1, 0.5])}
     if name == "autograd":
-        return {"lattices": [square_torus(6, 6), cubic_torus(3)],
+        return {"lattices": [square_torus(6, 6), cubic_torus(3),
+                             cubic_torus(3, pm_couplings(81, _PM_SEED_CUBE), seed=_PM_SEED_CUBE)],
                 "T": T_GRID(64), "h": np.linspace(-1.0, 1.0, 64)}
     raise KeyError(name)
 
