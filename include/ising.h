@@ -203,16 +203,19 @@ ising_status ising_bond_backward(const ising_plan *plan, const double *W_dev, do
 /* ------------------------------------------------------------------------ */
 
 /* Opaque batch plan: one plan per lattice (same rules as ising_plan_create,
- * with one tile width and one coupling-class count shared by all members so
- * a single kernel serves the batch) and a work list of (lattice, task) units
- * ordered largest lattice first.  Immutable after creation, except for the
+ * with one coupling-class count shared by all members so a single kernel
+ * serves the batch; each member keeps its own tile width, chunk width and LDS
+ * layout) and a work list of (lattice, task) units ordered largest lattice
+ * first.  Immutable after creation, except for the
  * device work counter: launches that use the same batch plan must not
  * overlap in time (serialise them on one stream). */
 typedef struct ising_batch_plan ising_batch_plan;
 
 /* n lattices (host array of n descriptors, read during the call only);
- * tune may be NULL (inner_bits is ignored; prefix_bits, tile_bits,
- * replicas, waves_per_block and max_blocks apply to every member). */
+ * tune may be NULL.  Each member's chunk width is tune.inner_bits (default
+ * 14, at most the member's N) unless tune.prefix_bits is given; tile_bits is
+ * an upper bound on each member's tile width; replicas, waves_per_block and
+ * max_blocks apply to every member. */
 ising_status ising_batch_plan_create(const ising_lattice *lattices, int32_t n, const ising_tune *tune,
                                      ising_batch_plan **plan);
 ising_status ising_batch_plan_destroy(ising_batch_plan *plan);

@@ -1,6 +1,6 @@
 """Autotuner for the enumeration's decomposition knobs.
 
-The plan's defaults (8-bit tile, ~16 tasks per block) are near the LDS
+The plan's defaults (8-bit tile, ~4 tasks per block) are near the LDS
 atomic ceiling for one large lattice.  A batch mixes lattices of different
 size, coordination and coupling spread, where chunk size (prefix_bits), tile
 width and histogram copies trade per-task set-up against load balance.  The

@@ -3,9 +3,10 @@
 // HIP graph.
 //
 // Each member is planned exactly like a single lattice (same ordering, tile
-// walk and LDS histogram; see enumerate.hip), with one tile width and one
-// coupling-class count shared by the batch so one kernel instantiation serves
-// every member.  The work list holds (member, task) units - a task is one
+// walk and LDS histogram; see enumerate.hip), with one coupling-class count
+// shared by the batch so one kernel instantiation serves every member; each
+// member keeps its own tile width, chunk width, LDS copy count and thread ->
+// chunk table.  The work list holds (member, task) units - a task is one
 // chunk per thread of a block - ordered largest member first; blocks take
 // units from a device counter.  A block keeps one member's histogram in LDS
 // and flushes it to that member's table whenever it moves to another member
