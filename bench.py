@@ -228,7 +228,8 @@ def bench_autograd(plain_rate: float, reps: int) -> dict:
         bms = _median_ms(bwd, reps)
         configs = 1 << lat.n_spins
         out["lattices"].append({
-            "lattice": f"{lat.kind} {lat.describe()['dims']} (N={lat.n_spins}, {lat.n_bonds} bonds)",
+            "lattice": f"{lat.kind} {lat.describe()['dims']} (N={lat.n_spins}, {lat.n_bonds} bonds, "
+                       + ("J=1)" if set(int(v) for v in lat.bond_J) == {1} else f"seeded +-J, seed {lat.seed})"),
             "forward_ms": fms,
             "backward_ms": bms,
             "backward_value": configs / (bms * 1e-3),
