@@ -20,15 +20,21 @@
 //     compile-time fact of the unrolled Gray sequence, so a configuration
 //     costs one load, one integer add and about two FP64 adds.
 //   * per tile block (walk) q the sums S_q = sum W and Y_q,i = sum W s_i are
-//     folded into chunk totals: sum W, sum W s_t, sum W s_m, sum W s_t s_m,
-//     sum W s_m1 s_m2 (s_m, the middle spins, are fixed within a block).
-//   * at the chunk's end every coupled pair takes its sum from one of these
-//     (tile-middle, middle-middle), from sum W s_a times the sign of a prefix
-//     spin b (inner-prefix pairs), or from sum W times s_a s_b (both in the
-//     prefix).  Each pair's value is summed over the wave (a DPP tree) and
-//     added to a per-wave LDS accumulator; blocks write per-pair partial sums and a
-//     second kernel adds them in block order and scatters them to the input
-//     bonds.  Every sum runs in a fixed order, so results are reproducible.
+//     folded into the lane's running totals: sum W, sum W s_t, sum W s_m,
+//     sum W s_t s_m, sum W s_m1 s_m2 (s_m, the middle spins, are fixed within
+//     a block).  They run over all of the lane's chunks, never reset.
+//   * every coupled pair takes its sum from one of these (tile-middle,
+//     middle-middle), from sum W s_a times the sign of a prefix spin b
+//     (inner-prefix pairs), or from sum W times s_a s_b (both in the prefix).
+//     A thread's chunks share their low 9 bits (the block has 512 threads),
+//     so prefix spins there are fixed per thread; the rest ("task" bits) are
+//     the same for the whole block within one task.  Pairs with no task bit
+//     are summed over the wave once, at the end; the others after every task,
+//     from the growth of the wave totals they need (about a dozen per task
+//     rather than one per pair).  Wave sums use a DPP tree and go to per-wave
+//     LDS accumulators; blocks write per-pair partial sums and a second
+//     kernel adds them in block order and scatters them to the input bonds.
+//     Every sum runs in a fixed order, so results are reproducible.
 // The tile is an independent set of the coupling graph, so there are no
 // tile-tile pairs.
 #include <hip/hip_runtime.h>
@@ -160,7 +166,7 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
   }
 }
 
-// Chunk totals of one lane (sums over the chunk's 2^k configurations).
+// Running totals of one lane over all the configurations it has walked.
 template <int TJ>
 struct ChunkSums {
   double S;                 // W
@@ -182,6 +188,9 @@ struct ChunkSums {
 #pragma unroll
     for (int j = 0; j < 6; ++j) M2[j] = 0.0;
   }
+
+  // W s_a for inner bit a (tile, then middle)
+  __device__ __forceinline__ double inner(int a) const { return a < TJ ? Yt[a < TJ ? a : 0] : Ym[a < TJ ? 0 : a - TJ]; }
 };
 
 template <int TJ, int NC>
@@ -246,10 +255,63 @@ __device__ __forceinline__ double wave_total(double v) {
   return v;
 }
 
-// Add every pair's chunk sum, summed over the wave, to the wave's accumulator.
+// v s_b, and v s_a s_b, for the spins of bits a and b of state x
+__device__ __forceinline__ double signed_by(uint64_t x, int b, double v) { return ((x >> b) & 1u) ? v : -v; }
+__device__ __forceinline__ double signed_by2(uint64_t x, int a, int b, double v) {
+  return (((x >> a) ^ (x >> b)) & 1u) ? -v : v;
+}
+
+// After a task: pairs with a task bit b, whose sign is the same for the whole
+// block but changes from task to task.  The task's part of a lane sum is the
+// growth of its wave total since the previous task (prev[], per wave, kept by
+// lane 63, which holds the totals); it is added to the pair's accumulator with
+// the task's sign of b.  One wave reduction per inner bit with task-bit
+// partners, per lane-fixed bit with task-bit partners (of W s_a, s_a fixed per
+// lane), and one of W for the task-task pairs.
 template <int TJ>
-__device__ inline void flush_pairs(const BondTables *__restrict__ T, const ChunkSums<TJ> &cs, uint64_t x0,
-                                   double *acc, bool last_lane) {
+__device__ inline void flush_task(const BondTables *__restrict__ T, const ChunkSums<TJ> &cs, uint64_t x0,
+                                  double *acc, double *prev, bool last_lane) {
+#pragma unroll
+  for (int a = 0; a < TJ + kBwMid; ++a) {
+    const int e0 = T->it_start[a], e1 = T->it_start[a + 1];
+    if (e0 < e1) {
+      const double c = wave_total(cs.inner(a));
+      if (last_lane) {
+        const double r = c - prev[a];
+        prev[a] = c;
+        for (int e = e0; e < e1; ++e) acc[T->it_pair[e]] += signed_by(x0, T->it_bit[e], r);
+      }
+    }
+  }
+  const int n_ltg = T->n_ltg;
+  for (int g = 0; g < n_ltg; ++g) {
+    const double c = wave_total(signed_by(x0, T->ltg_a[g], cs.S));
+    if (last_lane) {
+      const double r = c - prev[kInner + g];
+      prev[kInner + g] = c;
+      const int e1 = T->ltg_start[g + 1];
+      for (int e = T->ltg_start[g]; e < e1; ++e) acc[T->lt_pair[e]] += signed_by(x0, T->lt_bit[e], r);
+    }
+  }
+  const int n_tt = T->n_tt;
+  if (n_tt > 0) {
+    const double c = wave_total(cs.S);
+    if (last_lane) {
+      const double r = c - prev[kInner + kLaneBits];
+      prev[kInner + kLaneBits] = c;
+      for (int e = 0; e < n_tt; ++e)
+        acc[T->tt_pair[e]] += signed_by2(x0, T->tt_a[e], T->tt_b[e], r);
+    }
+  }
+}
+
+// At the end: pairs whose sign pattern is fixed per lane (x: the lane's
+// lane-fixed bits in place, other prefix bits 0), one wave reduction each:
+// tile-middle and middle-middle pairs from Q and M2, inner a - lane-fixed b
+// from W s_a times s_b, lane-fixed pairs from W times s_a s_b.
+template <int TJ>
+__device__ inline void flush_end(const BondTables *__restrict__ T, const ChunkSums<TJ> &cs, uint64_t x,
+                                 double *acc, bool last_lane) {
 #pragma unroll
   for (int m = 0; m < kBwMid; ++m)
 #pragma unroll
@@ -270,18 +332,16 @@ __device__ inline void flush_pairs(const BondTables *__restrict__ T, const Chunk
   }
 #pragma unroll
   for (int a = 0; a < TJ + kBwMid; ++a) {
-    const double V = a < TJ ? cs.Yt[a < TJ ? a : 0] : cs.Ym[a < TJ ? 0 : a - TJ];
-    const int e1 = T->ip_start[a + 1];
-    for (int e = T->ip_start[a]; e < e1; ++e) {
-      const double v = wave_total(((x0 >> T->ip_bit[e]) & 1u) ? V : -V);
-      if (last_lane) acc[T->ip_pair[e]] += v;
+    const int e1 = T->il_start[a + 1];
+    for (int e = T->il_start[a]; e < e1; ++e) {
+      const double v = wave_total(signed_by(x, T->il_bit[e], cs.inner(a)));
+      if (last_lane) acc[T->il_pair[e]] += v;
     }
   }
-  const int n_pp = T->n_pp;
-  for (int e = 0; e < n_pp; ++e) {
-    const bool differ = (((x0 >> T->pp_a[e]) ^ (x0 >> T->pp_b[e])) & 1u) != 0;
-    const double v = wave_total(differ ? -cs.S : cs.S);
-    if (last_lane) acc[T->pp_pair[e]] += v;
+  const int n_ll = T->n_ll;
+  for (int e = 0; e < n_ll; ++e) {
+    const double v = wave_total(signed_by2(x, T->ll_a[e], T->ll_b[e], cs.S));
+    if (last_lane) acc[T->ll_pair[e]] += v;
   }
 }
 
@@ -303,22 +363,28 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
   }
   const int n_pairs = T->n_pairs;
   double *acc_all = lds + T->wt_bytes / 8;
-  for (int i = threadIdx.x; i < kBwWaves * n_pairs; i += blockDim.x) acc_all[i] = 0.0;
+  double *prev_all = acc_all + kBwWaves * n_pairs;
+  for (int i = threadIdx.x; i < kBwWaves * (n_pairs + kPrevSlots); i += blockDim.x) acc_all[i] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const bool last_lane = lane == kWave - 1;
   double *acc = acc_all + wave * n_pairs;
+  double *prev = prev_all + wave * kPrevSlots;
   SiteTable<NC> st;
   st.load(P, lane);
   const uint32_t rep_bytes = uint32_t(lane & (rw - 1)) * 8u;
+  // A block has kBwWaves * kWave = 2^kLaneBits threads, so a thread's chunks
+  // share their low kLaneBits bits (its offset).
   const uint32_t offset = T->lane_chunk[threadIdx.x];
   ChunkSums<TJ> cs;
+  cs.clear();
   for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
-    const uint64_t chunk = t * blockDim.x + offset;
+    const uint64_t chunk = (t << kLaneBits) + offset;
     const uint64_t x0 = chunk << st.k;
-    cs.clear();
     if (chunk < n_chunks) bond_chunk<TJ, NC>(st, x0, rep_bytes, wt, cs);
-    flush_pairs<TJ>(T, cs, x0, acc, lane == kWave - 1);
+    flush_task<TJ>(T, cs, x0, acc, prev, last_lane);
   }
+  flush_end<TJ>(T, cs, uint64_t(offset) << st.k, acc, last_lane);
   __syncthreads();
   for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
     double s = 0.0;
@@ -441,6 +507,7 @@ extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *
   int cus = 0;
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const uint64_t n_chunks = uint64_t(1) << (bp->geo.n - bp->geo.inner);
+  static_assert(kBwWaves * kWave == 1 << kLaneBits, "a block walks 2^kLaneBits chunks per task");
   const uint64_t block = uint64_t(kBwWaves) * kWave;
   const uint64_t n_tasks = (n_chunks + block - 1) / block;
   const int grid = int(std::min<uint64_t>({n_tasks, uint64_t(cus), uint64_t(kMaxBwBlocks)}));

@@ -49,8 +49,9 @@ BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const 
   // A 64-bit LDS read serves 32 lanes per cycle from 32 banks of 8 bytes;
   // double (bin * rw + copy) sits in bank (bin * rw + copy) mod 32.
   const int Wb = (n + 4) & ~3;
-  // weight-table copies that fit next to the per-wave pair accumulators
-  const int64_t acc_bytes = int64_t(kBwWaves) * std::max(n_pairs, 1) * 8;
+  // weight-table copies that fit next to the per-wave pair accumulators and
+  // previous cumulative sums
+  const int64_t acc_bytes = int64_t(kBwWaves) * (std::max(n_pairs, 1) + kPrevSlots) * 8;
   const int64_t copy_bytes = int64_t(d.n_ec) * Wb * 8;
   int rw = 8;
   while (rw > 1 && copy_bytes * rw + acc_bytes > kHistBytes) rw >>= 1;
@@ -83,37 +84,62 @@ BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const 
   for (auto &row : t.qpair)
     for (auto &v : row) v = -1;
   for (auto &v : t.m2pair) v = -1;
-  std::vector<std::vector<std::pair<int, int>>> ip(static_cast<size_t>(kb));   // inner bit -> (pair, prefix bit)
+  const int lf_end = kb + kLaneBits;   // prefix bits [kb, lf_end) are lane-fixed
+  std::vector<std::vector<std::pair<int, int>>> it(kInner), il(kInner), lt(kLaneBits);
   for (int q = 0; q < n_pairs; ++q) {
     int a = p->bit_of_site[pairs[q].first], b = p->bit_of_site[pairs[q].second];
     if (a > b) std::swap(a, b);
     if (b < TJ) return bad("internal: bond pair inside the tile");   // the tile holds no listed pair
-    if (b < kb) {
+    if (b < kb) {                      // both inner: per-lane chunk sums
       if (a < TJ) t.qpair[b - TJ][a] = (int16_t)q;
       else {
         const int m1 = a - TJ, m2 = b - TJ;
         t.m2pair[m1 * (7 - m1) / 2 + (m2 - m1 - 1)] = (int16_t)q;
       }
-    } else if (a < kb) {
-      ip[size_t(a)].push_back({q, b});
-    } else {
-      t.pp_pair[t.n_pp] = (int16_t)q;
-      t.pp_a[t.n_pp] = (uint8_t)a;
-      t.pp_b[t.n_pp] = (uint8_t)b;
-      ++t.n_pp;
+    } else if (a < kb) {               // inner - prefix
+      (b < lf_end ? il : it)[size_t(a)].push_back({q, b});
+    } else if (b < lf_end) {           // both lane-fixed
+      t.ll_pair[t.n_ll] = (int16_t)q;
+      t.ll_a[t.n_ll] = (uint8_t)a;
+      t.ll_b[t.n_ll] = (uint8_t)b;
+      ++t.n_ll;
+    } else if (a < lf_end) {           // lane-fixed - task
+      lt[size_t(a - kb)].push_back({q, b});
+    } else {                           // both task bits
+      t.tt_pair[t.n_tt] = (int16_t)q;
+      t.tt_a[t.n_tt] = (uint8_t)a;
+      t.tt_b[t.n_tt] = (uint8_t)b;
+      ++t.n_tt;
     }
   }
-  int e = 0;
-  for (int a = 0; a <= kMaxTile + kBwMid; ++a) {
-    t.ip_start[a] = (int16_t)e;
-    if (a < kb)
-      for (auto &pr : ip[size_t(a)]) {
-        t.ip_pair[e] = (int16_t)pr.first;
-        t.ip_bit[e] = (uint8_t)pr.second;
-        ++e;
-      }
+  int e = 0, f = 0;
+  for (int a = 0; a <= kInner; ++a) {
+    t.it_start[a] = (int16_t)e;
+    t.il_start[a] = (int16_t)f;
+    if (a == kInner) break;
+    for (auto &pr : it[size_t(a)]) {
+      t.it_pair[e] = (int16_t)pr.first;
+      t.it_bit[e++] = (uint8_t)pr.second;
+    }
+    for (auto &pr : il[size_t(a)]) {
+      t.il_pair[f] = (int16_t)pr.first;
+      t.il_bit[f++] = (uint8_t)pr.second;
+    }
   }
-  t.n_ip = e;
+  int g = 0;
+  e = 0;
+  for (int l = 0; l < kLaneBits; ++l) {
+    if (lt[size_t(l)].empty()) continue;
+    t.ltg_a[g] = (uint8_t)(kb + l);
+    t.ltg_start[g] = (int16_t)e;
+    for (auto &pr : lt[size_t(l)]) {
+      t.lt_pair[e] = (int16_t)pr.first;
+      t.lt_bit[e++] = (uint8_t)pr.second;
+    }
+    ++g;
+  }
+  t.ltg_start[g] = (int16_t)e;
+  t.n_ltg = g;
 
   // Which chunk of a task each thread walks: with 8 copies, lanes sharing a
   // copy get chunks of four different n_up mod 4 (balance_lane_chunks).
