@@ -129,3 +129,40 @@ def bond_split(n_spins: int, bond_i, bond_j, bond_J, n_threads: int | None = Non
     if rc != 0:
         raise ValueError(f"oracle_bond_split failed ({rc})")
     return g, gp[:nb]
+
+
+def tm_torus_bond_split(Jh, Jv, direction: int, x: int, y: int, n_threads: int | None = None):
+    """(g, gp) of one bond of a square torus from the transfer matrix, for
+    tori too large for bond_split's brute force.
+
+    The bond couples (x, y) to (x+1, y) when direction is 0 (coupling Jh[y][x])
+    and to (x, y+1) when it is 1 (Jv[y][x]).  Eq. (1) makes H depend on the
+    bond's coupling J_b only through -J_b s_i s_j, so raising J_b by D > 2S
+    moves every configuration with s_i s_j = +1 from E to E - D < -S and every
+    one with s_i s_j = -1 to E + D > S: the shifted torus's table holds the two
+    halves apart, each an exact copy of its part of g.  g[E + S][n_up] is the
+    unshifted table, gp its part with s_i s_j = +1 (as bond_split).
+    """
+    Jh = np.array(Jh, dtype=np.int64)
+    Jv = np.array(Jv, dtype=np.int64)
+    S = int(np.abs(Jh).sum() + np.abs(Jv).sum())
+    D = 2 * S + 1
+    grid = Jh if direction == 0 else Jv
+    Jb = int(grid[y, x])
+    grid[y, x] = Jb + D
+    S2 = S - abs(Jb) + abs(Jb + D)
+    g2 = tm_torus(Jh, Jv, n_threads)
+    # rows of E' in [-S - D, S + D] (the shifted table spans only [-S2, S2])
+    pad = S + D - S2
+    g2 = np.concatenate([np.zeros((pad, g2.shape[1]), np.uint64), g2, np.zeros((pad, g2.shape[1]), np.uint64)])
+    ne = 2 * S + 1
+    lo = 0              # row of E' = E - D for E = -S: configurations with s_i s_j = +1
+    hi = 2 * D          # row of E' = E + D for E = -S: configurations with s_i s_j = -1
+    gp = g2[lo:lo + ne].copy()
+    gm = g2[hi:hi + ne].copy()
+    rest = g2.copy()
+    rest[lo:lo + ne] = 0
+    rest[hi:hi + ne] = 0
+    if rest.any():
+        raise AssertionError("shifted bond left counts outside its two energy windows")
+    return gp + gm, gp

@@ -105,6 +105,71 @@ def test_bond_backward_matches_oracle(api, name):
     np.testing.assert_allclose(dJ, ref, rtol=0, atol=1e-13 * scale)
 
 
+def _bond_kinds(plan, lat):
+    """Where each bond's two spins sit in the backward walk: inner (tile and up
+    to 4 middle bits), lane (the next 9 bits, fixed per thread) or task (the
+    rest, fixed per block and task)."""
+    N, TJ = lat.n_spins, plan.tile_bits
+    kb = TJ + min(4, N - TJ)
+
+    def kind(bit):
+        return "inner" if bit < kb else ("lane" if bit < kb + 9 else "task")
+
+    out = {}
+    for b, (i, j) in enumerate(zip(lat.bond_i, lat.bond_j)):
+        a, c = sorted((int(plan.bit_of_site[i]), int(plan.bit_of_site[j])))
+        out.setdefault(kind(a) + "-" + kind(c), []).append(b)
+    return out
+
+
+def _torus_bond(lat, b):
+    Lx = lat.dims[0]
+    u, d = divmod(b, 2)
+    return d, u % Lx, u // Lx
+
+
+def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api):
+    # The full 2^40 backward on the +-J 8x5 torus (about 2000 tasks per block),
+    # with a random weight table; two bonds of every kind of bit pair, each
+    # against the oracle's transfer-matrix split of that bond.
+    lat = L.workload("torus8x5_pm")["lattice"]
+    Jh, Jv = L.torus_coupling_grids(lat)
+    g = native.tm_torus(Jh, Jv)
+    rng = np.random.default_rng(8_5)
+    W = np.where(g > 0, rng.standard_normal(g.shape) * np.exp(-rng.uniform(0, 3, g.shape)), 0.0)
+    plan = api.Plan(lat)
+    kinds = _bond_kinds(plan, lat)
+    print("8x5 bond kinds:", {k: len(v) for k, v in sorted(kinds.items())}, flush=True)
+    assert {"inner-task", "lane-task", "task-task", "inner-inner"} <= set(kinds)
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    scale = (np.abs(W) * g.astype(np.float64)).sum()
+    for k in sorted(kinds):
+        for b in kinds[k][:2]:
+            g2, gp = native.tm_torus_bond_split(Jh, Jv, *_torus_bond(lat, b))
+            assert np.array_equal(g2, g)
+            ref = grad.bond_grad_from_weights(g, gp[None], W)[0]
+            assert abs(dJ[b] - ref) <= 1e-13 * scale, (k, b, dJ[b], ref, scale)
+
+
+def test_torus6x6_backward_random_weights_equal_on_every_bond(api):
+    # On the edge-transitive 6x6 torus at uniform J every bond has the same
+    # split table, so for any W(E, M) all 72 bond sums agree; one horizontal and
+    # one vertical bond are checked against the transfer-matrix split.
+    lat = L.square_torus(6, 6)
+    Jh, Jv = L.torus_coupling_grids(lat)
+    g = native.tm_torus(Jh, Jv)
+    rng = np.random.default_rng(36)
+    W = np.where(g > 0, rng.uniform(-1, 1, g.shape), 0.0)
+    plan = api.Plan(lat)
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    scale = (np.abs(W) * g.astype(np.float64)).sum()
+    np.testing.assert_allclose(dJ, dJ.mean(), rtol=0, atol=1e-13 * scale)
+    for b in (0, 1):
+        _, gp = native.tm_torus_bond_split(Jh, Jv, *_torus_bond(lat, b))
+        ref = grad.bond_grad_from_weights(g, gp[None], W)[0]
+        assert abs(dJ[b] - ref) <= 1e-13 * scale, (b, dJ[b], ref, scale)
+
+
 def test_bond_backward_is_reproducible_and_matches_small_tune(api):
     lat = LATS["cubic3_pm"]
     g, gp = _split("cubic3_pm")

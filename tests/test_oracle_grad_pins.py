@@ -208,3 +208,19 @@ def test_planted_dropped_bond_breaks_energy_identity():
     lhs = sum(int(J) * sig[b] for b, J in enumerate(lat.bond_J) if b != 4)
     E = np.arange(-S, S + 1, dtype=object)[:, None]
     assert not np.array_equal(lhs, -E * g.astype(object))
+
+
+@pytest.mark.parametrize("lat", [L.square_torus(4, 5, L.pm_couplings(40, 5)),
+                                 L.square_torus(5, 3, L.choice_couplings(30, 3)),
+                                 L.square_torus(3, 3)], ids=lambda l: "x".join(map(str, l.dims)))
+def test_transfer_matrix_bond_split_matches_brute_force(lat):
+    # The shifted-coupling transfer matrix (for tori too large to enumerate on
+    # the CPU) gives every bond's split table exactly as the brute force does.
+    g, gp = _split(lat)
+    Jh, Jv = L.torus_coupling_grids(lat)
+    Lx = lat.dims[0]
+    for b in range(lat.n_bonds):
+        u, d = divmod(b, 2)
+        g2, gp2 = native.tm_torus_bond_split(Jh, Jv, d, u % Lx, u // Lx)
+        np.testing.assert_array_equal(g2, g)
+        np.testing.assert_array_equal(gp2, gp[b], err_msg=f"bond {b}")
