@@ -33,7 +33,7 @@
 //     from the growth of the wave totals they need (about a dozen per task
 //     rather than one per pair).  Wave sums use a DPP tree and go to per-wave
 //     LDS accumulators; blocks write per-pair partial sums and a second
-//     kernel adds them in block order and scatters them to the input bonds.
+//     kernel adds them in a fixed order and scatters them to the input bonds.
 //     Every sum runs in a fixed order, so results are reproducible.
 // The tile is an independent set of the coupling graph, so there are no
 // tile-tile pairs.
@@ -354,12 +354,25 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
   __shared__ __align__(16) double lds[kHistBytes / 8];
   const char *wt = reinterpret_cast<const char *>(lds);
   const int rw = T->rw, Wc = P->W, n_m = P->n_m;
-  const int words = P->n_ec * Wc * rw;
-  for (int w = threadIdx.x; w < words; w += blockDim.x) {
-    const int bin = w / rw;
-    const int e_idx = bin / Wc, nu = bin - e_idx * Wc;
-    const int E = P->e_base + e_idx * P->estep;
-    lds[w] = nu < n_m ? Wd[size_t(E - P->e_min) * n_m + nu] : 0.0;
+  const int bins = P->n_ec * Wc;
+  // Each bin's weight is read from global memory once (eight loads in flight
+  // per thread) and written to its rw copies.
+  constexpr int kFill = 8;
+  for (int base = 0; base < bins; base += kFill * int(blockDim.x)) {
+    double v[kFill];
+#pragma unroll
+    for (int j = 0; j < kFill; ++j) {
+      const int bin = base + j * int(blockDim.x) + int(threadIdx.x);
+      const int e_idx = bin / Wc, nu = bin - e_idx * Wc;
+      const int E = P->e_base + e_idx * P->estep;
+      v[j] = (bin < bins && nu < n_m) ? Wd[size_t(E - P->e_min) * n_m + nu] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kFill; ++j) {
+      const int bin = base + j * int(blockDim.x) + int(threadIdx.x);
+      if (bin < bins)
+        for (int c = 0; c < rw; ++c) lds[bin * rw + c] = v[j];
+    }
   }
   const int n_pairs = T->n_pairs;
   double *acc_all = lds + T->wt_bytes / 8;
@@ -393,16 +406,30 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
   }
 }
 
-// dJ[b] = sum over blocks (in order) of the partial sums of b's pair.
-__global__ void k_bond_finish(const BondTables *__restrict__ T, const int32_t *__restrict__ pair_of_bond,
-                              const double *__restrict__ partial, int blocks, double *__restrict__ dJ) {
+// dJ[b] = the sum over blocks of the partial sums of b's pair.  One block per
+// pair: thread t adds the partials of blocks t, t + 256, ... in order, then a
+// fixed tree over the threads, so the result does not depend on timing; the
+// block then writes the total to every input bond of its pair.
+constexpr int kFinishThreads = 256;
+
+__global__ __launch_bounds__(kFinishThreads) void k_bond_finish(const BondTables *__restrict__ T,
+                                                                const int32_t *__restrict__ pair_of_bond,
+                                                                const double *__restrict__ partial, int blocks,
+                                                                double *__restrict__ dJ) {
+  __shared__ double sh[kFinishThreads];
   const int n_pairs = T->n_pairs, n_bonds = T->n_bonds;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_bonds; b += gridDim.x * blockDim.x) {
-    const int p = pair_of_bond[b];
-    double s = 0.0;
-    for (int k = 0; k < blocks; ++k) s += partial[size_t(k) * n_pairs + p];
-    dJ[b] = s;
+  const int p = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < blocks; k += kFinishThreads) s += partial[size_t(k) * n_pairs + p];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kFinishThreads / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
   }
+  const double total = sh[0];
+  for (int b = threadIdx.x; b < n_bonds; b += kFinishThreads)
+    if (pair_of_bond[b] == p) dJ[b] = total;
 }
 
 // {DevPlan, BondTables, pair_of_bond} of the backward on `device` (lazy).
@@ -515,8 +542,8 @@ extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *
   double *partial = static_cast<double *>(workspace);
   st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, dP, dT, W_dev, n_chunks, n_tasks, grid, partial, s);
   if (st != ISING_OK) return st;
-  const int fb = std::min((p->n_bonds + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(fb)), dim3(256), 0, s, dT, dmap, partial, grid, dJ_dev);
+  hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(bp->tables.n_pairs)), dim3(kFinishThreads), 0, s, dT, dmap,
+                     partial, grid, dJ_dev);
   HIP_TRY(hipGetLastError());
   return ISING_OK;
 }

@@ -21,7 +21,11 @@ BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const 
   if (!bp) return nullptr;
   const DevPlan &d = p->dev;
   const int n = d.n, TJ = d.tile;
-  const int mj = std::min(kBwMid, n - TJ);
+  // Middle bits: up to kBwMid, fewer on small lattices so that the chunks
+  // still make 2^kFillTaskBits tasks of 2^kLaneBits (one block per CU of a
+  // 256-CU device) where the spins allow.
+  constexpr int kFillTaskBits = 8;
+  const int mj = std::max(0, std::min(kBwMid, n - TJ - kLaneBits - kFillTaskBits));
   const int kb = TJ + mj;
   auto bad = [&](const std::string &m) {
     bp->status = ISING_EUNSUPPORTED;

@@ -170,6 +170,25 @@ def test_torus6x6_backward_random_weights_equal_on_every_bond(api):
         assert abs(dJ[b] - ref) <= 1e-13 * scale, (b, dJ[b], ref, scale)
 
 
+@pytest.mark.parametrize("n,mid", [(21, 1), (23, 3), (25, 4), (19, 0)])
+def test_bond_backward_middle_widths(api, n, mid):
+    # With a 3-bit tile the backward takes mid = min(4, n - 3 - 17) middle bits
+    # (fewer on small lattices, to keep 256 tasks), so these sizes cover every
+    # middle width, and with it every split of the spins between middle,
+    # thread-fixed and task bits.
+    lat = L.random_bond_lattice(n, 3 * n, 100 + n, values=(-1, 1))
+    assert mid == max(0, min(4, n - 3 - 17))
+    g, gp = native.bond_split(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J)
+    rng = np.random.default_rng(n)
+    W = np.where(g > 0, rng.standard_normal(g.shape), 0.0)
+    plan = api.Plan(lat, api.Tune(tile_bits=3))
+    assert plan.tile_bits == 3
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    ref = grad.bond_grad_from_weights(g, gp, W)
+    scale = (np.abs(W) * g.astype(np.float64)).sum()
+    np.testing.assert_allclose(dJ, ref, rtol=0, atol=1e-13 * scale)
+
+
 def test_bond_backward_is_reproducible_and_matches_small_tune(api):
     lat = LATS["cubic3_pm"]
     g, gp = _split("cubic3_pm")
