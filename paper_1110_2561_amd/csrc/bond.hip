@@ -168,7 +168,7 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
 
 // Running totals of one lane over all the configurations it has walked.
 template <int TJ>
-struct ChunkSums {
+struct LaneSums {
   double S;                 // W
   double Yt[TJ];            // W s_t, tile spins
   double Ym[kBwMid];        // W s_m, middle spins
@@ -195,7 +195,7 @@ struct ChunkSums {
 
 template <int TJ, int NC>
 __device__ inline void bond_chunk(const SiteTable<NC> &st, uint64_t x0, uint32_t rep_bytes, const char *wt,
-                                  ChunkSums<TJ> &cs) {
+                                  LaneSums<TJ> &cs) {
   uint32_t A;
   int32_t D[TJ];
   chunk_start<TJ, NC>(st, x0, rep_bytes, A, D);
@@ -269,7 +269,7 @@ __device__ __forceinline__ double signed_by2(uint64_t x, int a, int b, double v)
 // partners, per lane-fixed bit with task-bit partners (of W s_a, s_a fixed per
 // lane), and one of W for the task-task pairs.
 template <int TJ>
-__device__ inline void flush_task(const BondTables *__restrict__ T, const ChunkSums<TJ> &cs, uint64_t x0,
+__device__ inline void flush_task(const BondTables *__restrict__ T, const LaneSums<TJ> &cs, uint64_t x0,
                                   double *acc, double *prev, bool last_lane) {
 #pragma unroll
   for (int a = 0; a < TJ + kBwMid; ++a) {
@@ -310,7 +310,7 @@ __device__ inline void flush_task(const BondTables *__restrict__ T, const ChunkS
 // tile-middle and middle-middle pairs from Q and M2, inner a - lane-fixed b
 // from W s_a times s_b, lane-fixed pairs from W times s_a s_b.
 template <int TJ>
-__device__ inline void flush_end(const BondTables *__restrict__ T, const ChunkSums<TJ> &cs, uint64_t x,
+__device__ inline void flush_end(const BondTables *__restrict__ T, const LaneSums<TJ> &cs, uint64_t x,
                                  double *acc, bool last_lane) {
 #pragma unroll
   for (int m = 0; m < kBwMid; ++m)
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
   // A block has kBwWaves * kWave = 2^kLaneBits threads, so a thread's chunks
   // share their low kLaneBits bits (its offset).
   const uint32_t offset = T->lane_chunk[threadIdx.x];
-  ChunkSums<TJ> cs;
+  LaneSums<TJ> cs;
   cs.clear();
   for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
     const uint64_t chunk = (t << kLaneBits) + offset;
