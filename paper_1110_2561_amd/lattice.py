@@ -108,6 +108,27 @@ class Lattice:
         return {"kind": self.kind, "dims": list(self.dims), "n_spins": self.n_spins,
                 "n_bonds": self.n_bonds, "seed": self.seed}
 
+    def to_json(self) -> str:
+        """A self-contained JSON descriptor: the bond list with its couplings
+        (bonds as [i, j, J] in input order) and the builder's description."""
+        import json
+        d = self.describe()
+        d["bonds"] = [[int(i), int(j), int(J)] for i, j, J in zip(self.bond_i, self.bond_j, self.bond_J)]
+        return json.dumps(d)
+
+    @staticmethod
+    def from_json(text: str) -> "Lattice":
+        """The lattice of a descriptor written by to_json (bond order kept)."""
+        import json
+        d = json.loads(text)
+        b = np.asarray(d.get("bonds", []), dtype=np.int64).reshape(-1, 3)
+        if b.shape[0] != int(d.get("n_bonds", b.shape[0])):
+            raise ValueError("descriptor's n_bonds does not match its bond list")
+        if np.abs(b).max(initial=0) >= 2 ** 31:
+            raise ValueError("bond endpoints and couplings must fit int32")
+        return Lattice(int(d["n_spins"]), b[:, 0], b[:, 1], b[:, 2], kind=str(d.get("kind", "custom")),
+                       dims=tuple(int(x) for x in d.get("dims", ())), seed=d.get("seed"))
+
 
 def _couplings(n: int, J) -> np.ndarray:
     if np.isscalar(J):

@@ -56,3 +56,22 @@ def test_relabel_keeps_the_multiset():
     p = np.random.default_rng(0).permutation(12)
     r = lat.relabel(p)
     assert sorted(zip(r.bond_i, r.bond_j, r.bond_J)) == sorted(zip(p[lat.bond_i], p[lat.bond_j], lat.bond_J))
+
+
+@pytest.mark.parametrize("lat", [L.square_torus(8, 5, L.pm_couplings(80, 20111025), seed=20111025),
+                                 L.cubic_torus(3), L.triangular_free(19, 5, L.choice_couplings(L.triangular_free(19, 5).n_bonds, 2)),
+                                 L.Lattice(3, [0, 0], [1, 1], [2, -2]), L.Lattice(4, [], [], [])],
+                         ids=lambda l: f"{l.kind}{l.n_spins}")
+def test_json_round_trip(lat):
+    back = L.Lattice.from_json(lat.to_json())
+    assert back.n_spins == lat.n_spins and back.kind == lat.kind and back.dims == lat.dims
+    assert back.seed == lat.seed
+    for a in ("bond_i", "bond_j", "bond_J"):
+        np.testing.assert_array_equal(getattr(back, a), getattr(lat, a))
+
+
+def test_json_descriptor_errors():
+    with pytest.raises(ValueError):
+        L.Lattice.from_json('{"n_spins": 3, "n_bonds": 2, "bonds": [[0, 1, 1]]}')
+    with pytest.raises(ValueError):
+        L.Lattice.from_json('{"n_spins": 3, "bonds": [[0, 1, 4294967296]]}')
