@@ -161,6 +161,19 @@ def test_checkpoint_and_resume(api, tmp_path):
     np.testing.assert_array_equal(resumed.cpu().numpy(), whole)
 
 
+def test_checkpoint_runner_resumes(api, tmp_path):
+    """The library's checkpointed runner on the GPU: stopped after two pieces,
+    resumed by a fresh plan, equal to the transfer-matrix table (8x5 +-J)."""
+    from paper_1110_2561_amd import checkpoint
+    lat = L.workload("torus8x5_pm")["lattice"]
+    path = str(tmp_path / "run.npz")
+    g, done = checkpoint.run(api.Plan(lat), path, max_pieces=2)
+    assert not done
+    g, done = checkpoint.run(api.Plan(lat), path)
+    assert done
+    np.testing.assert_array_equal(g.cpu().numpy(), native.tm_torus(*L.torus_coupling_grids(lat)))
+
+
 LARGE = {
     "torus6x6": L.workload("torus6x6")["lattice"],
     "torus8x5_pm": L.workload("torus8x5_pm")["lattice"],
