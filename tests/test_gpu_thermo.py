@@ -79,3 +79,26 @@ def test_thermo_argument_errors(api):
         api.log_z(g, -9, 8, [1.0], [0.0])        # n_m != N + 1
     empty = api.log_z(g, -9, 9, [], [0.0])
     assert empty.shape == (0, 1)
+
+
+def test_command_line_table_and_thermo(api, tmp_path):
+    """The command line (run in-process): the 4x4 table it writes is Table 1,
+    its log Z matches the oracle, and the +-J 4x5 halved run writes the
+    brute-force table."""
+    import json
+
+    from conftest import load_table1
+    from paper_1110_2561_amd import __main__ as cli
+    from paper_1110_2561_amd import table
+    out, th = tmp_path / "g.txt", tmp_path / "th.json"
+    assert cli.main(["torus:4x4", "--table", str(out), "--T", "0.5:5:4", "--h", "0,0.1", "--thermo", str(th)]) == 0
+    assert {(e, m): c for c, m, e in table.read(str(out))} == load_table1()
+    d = json.loads(th.read_text())
+    lat = L.square_torus(4, 4)
+    g = native.count_all(16, lat.bond_i, lat.bond_j, lat.bond_J)
+    ref = thermo.log_z(g, -32, 16, np.array(d["T"]), np.array(d["h"]))
+    np.testing.assert_allclose(np.array(d["log_z"]), ref, rtol=1e-12)
+    assert cli.main(["torus:4x5", "--pm", "5", "--symmetric", "--table", str(out)]) == 0
+    lat = L.square_torus(4, 5, L.pm_couplings(40, 5))
+    g = native.count_all(20, lat.bond_i, lat.bond_j, lat.bond_J)
+    assert table.read(str(out)) == table.rows(g, -40, 20)
