@@ -24,7 +24,7 @@ constexpr int kInner = kMaxTile + kBwMid;   // inner bits (tile + middle) at mos
 // [0, TJ), middle [TJ, k = TJ + mj), then the prefix, whose first kLaneBits
 // bits are fixed for a thread ("lane-fixed", the chunk's offset in its task)
 // and the rest are the same for the whole block in one task ("task" bits)).
-// Per-lane chunk sums accumulate over all of a thread's chunks.  Pairs whose
+// Per-lane running sums accumulate over all of a thread's chunks.  Pairs whose
 // sign pattern is fixed per thread are reduced once at the end; pairs with a
 // task bit are reduced per task, as differences of the cumulative wave sums.
 struct BondTables {

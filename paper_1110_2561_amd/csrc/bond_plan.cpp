@@ -94,7 +94,7 @@ BondPlan *bond_plan_create(const ising_plan *p, const ising_lattice *lat, const 
     int a = p->bit_of_site[pairs[q].first], b = p->bit_of_site[pairs[q].second];
     if (a > b) std::swap(a, b);
     if (b < TJ) return bad("internal: bond pair inside the tile");   // the tile holds no listed pair
-    if (b < kb) {                      // both inner: per-lane chunk sums
+    if (b < kb) {                      // both inner: from the lane running sums
       if (a < TJ) t.qpair[b - TJ][a] = (int16_t)q;
       else {
         const int m1 = a - TJ, m2 = b - TJ;
