@@ -198,6 +198,18 @@ ising_status ising_bond_workspace(const ising_plan *plan, size_t *bytes);
 ising_status ising_bond_backward(const ising_plan *plan, const double *W_dev, double *dJ_dev,
                                  void *workspace, size_t workspace_bytes, void *stream);
 
+/* The same dJ from half of the configurations.  A global spin flip keeps the
+ * exchange energy E of Eq. (1) (it is even in the spins) and every product
+ * s_i s_j, and negates M, so the sum over all configurations equals the sum
+ * over those whose top spin (in the plan's order) is up, each weighted by
+ * W(E, M) + W(E, -M); the paper's closing section suggests using such
+ * symmetries.  About half the work; equal to ising_bond_backward up to FP64
+ * summation order.  Lattices with fewer than tile_bits + 10 spins take the
+ * full walk (the half is not a whole number of the walk's tasks there).
+ * Arguments, workspace and errors as ising_bond_backward. */
+ising_status ising_bond_backward_symmetric(const ising_plan *plan, const double *W_dev, double *dJ_dev,
+                                           void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batches: many lattices of uneven size in one persistent launch.          */
 /* ------------------------------------------------------------------------ */

@@ -189,15 +189,18 @@ def bin_weights(g: torch.Tensor, e_min: int, n_spins: int, T, h, logz: torch.Ten
     return W
 
 
-def bond_backward(plan: Plan, W: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """dJ[b] = sum over all configurations of W(E, M) s_i s_j per input bond (ising_bond_backward)."""
+def bond_backward(plan: Plan, W: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                  symmetric: bool = False) -> torch.Tensor:
+    """dJ[b] = sum over all configurations of W(E, M) s_i s_j per input bond (ising_bond_backward);
+    with symmetric, from the half of the configurations with the top spin up and weights
+    W(E, M) + W(E, -M) (ising_bond_backward_symmetric)."""
     if not (W.is_cuda and W.dtype == torch.float64 and W.is_contiguous() and tuple(W.shape) == (plan.n_e, plan.n_m)):
         raise ValueError(f"W must be a contiguous CUDA float64 tensor of shape {(plan.n_e, plan.n_m)}")
     nb = plan.lattice.n_bonds
     dJ = torch.empty(nb, dtype=torch.float64, device=W.device) if out is None else out
     ws = torch.empty(max(plan.bond_workspace_bytes, 8), dtype=torch.uint8, device=W.device)
-    _lib.check(_lib.ising_bond_backward(plan.handle, W.data_ptr(), dJ.data_ptr(), ws.data_ptr(), ws.numel(),
-                                        _stream_handle(stream)))
+    fn = _lib.ising_bond_backward_symmetric if symmetric else _lib.ising_bond_backward
+    _lib.check(fn(plan.handle, W.data_ptr(), dJ.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
     return dJ
 
 

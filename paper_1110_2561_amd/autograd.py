@@ -80,7 +80,7 @@ class _LogZ(torch.autograd.Function):
         if ctx.needs_input_grad[2]:
             W = api.bin_weights(model.g, model.plan.e_min, model.plan.n_spins, T.detach(), h.detach(), lz,
                                 go.detach())
-            gJ = api.bond_backward(model.plan, W)
+            gJ = api.bond_backward(model.plan, W, symmetric=model.symmetric_backward)
             if torch.is_grad_enabled():
                 gJ = _NotTwiceDifferentiable.apply(gJ, T, h, J)
         return gT, gh, gJ, None
@@ -91,11 +91,14 @@ class IsingLogZ:
     and differentiates Eq. (2) on any (T, h) grid.
 
     __call__(T [nT], h [nh], J [n_bonds] or None) -> log Z [nT, nh] (float64, on the GPU);
-    T and h are cast to float64 (differentiably).
+    T and h are cast to float64 (differentiably).  With symmetric_backward the
+    per-bond gradient walks half of the configurations (spin-flip symmetry,
+    api.bond_backward(symmetric=True)); the default recomputes all of them.
     """
 
-    def __init__(self, lattice: Lattice, tune: api.Tune | None = None):
+    def __init__(self, lattice: Lattice, tune: api.Tune | None = None, symmetric_backward: bool = False):
         self.lattice = lattice
+        self.symmetric_backward = bool(symmetric_backward)
         self.plan = api.Plan(lattice, tune)
         self.g = api.enumerate_g(self.plan)
         self._J = np.asarray(lattice.bond_J, dtype=np.float64)

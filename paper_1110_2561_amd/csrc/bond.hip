@@ -348,7 +348,10 @@ __device__ inline void flush_end(const BondTables *__restrict__ T, const LaneSum
 template <int TJ, int NC>
 __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
     const DevPlan *__restrict__ P, const BondTables *__restrict__ T, const double *__restrict__ Wd,
-    uint64_t n_chunks, uint64_t n_tasks, double *__restrict__ partial) {
+    uint64_t n_chunks, uint64_t t_begin, uint64_t n_tasks, int mirror, double *__restrict__ partial) {
+  // Tasks [t_begin, n_tasks).  With mirror set, the table holds
+  // W(E, M) + W(E, -M) (column n_up plus column N - n_up), for a walk over the
+  // half of the configurations whose top spin is up.
   // Static LDS (compile-time base): the weight table at offset 0, then the
   // per-wave pair accumulators.
   __shared__ __align__(16) double lds[kHistBytes / 8];
@@ -365,7 +368,8 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
       const int bin = base + j * int(blockDim.x) + int(threadIdx.x);
       const int e_idx = bin / Wc, nu = bin - e_idx * Wc;
       const int E = P->e_base + e_idx * P->estep;
-      v[j] = (bin < bins && nu < n_m) ? Wd[size_t(E - P->e_min) * n_m + nu] : 0.0;
+      const double *row = Wd + size_t(E - P->e_min) * n_m;
+      v[j] = (bin < bins && nu < n_m) ? (mirror ? row[nu] + row[n_m - 1 - nu] : row[nu]) : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < kFill; ++j) {
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
   const uint32_t offset = T->lane_chunk[threadIdx.x];
   LaneSums<TJ> cs;
   cs.clear();
-  for (uint64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
+  for (uint64_t t = t_begin + blockIdx.x; t < n_tasks; t += gridDim.x) {
     const uint64_t chunk = (t << kLaneBits) + offset;
     const uint64_t x0 = chunk << st.k;
     if (chunk < n_chunks) bond_chunk<TJ, NC>(st, x0, rep_bytes, wt, cs);
@@ -475,22 +479,24 @@ void bond_plan_free(BondPlan *b) {
 
 template <int TJ, int NC>
 static ising_status launch_bond(const DevPlan *dP, const BondTables *dT, const double *W, uint64_t n_chunks,
-                                uint64_t n_tasks, int grid, double *partial, hipStream_t s) {
+                                uint64_t t_begin, uint64_t n_tasks, int mirror, int grid, double *partial,
+                                hipStream_t s) {
   hipLaunchKernelGGL((k_bond_backward<TJ, NC>), dim3(grid), dim3(kBwWaves * kWave), 0, s, dP, dT, W, n_chunks,
-                     n_tasks, partial);
+                     t_begin, n_tasks, mirror, partial);
   HIP_TRY(hipGetLastError());
   return ISING_OK;
 }
 
 static ising_status bond_dispatch(int tile, int n_classes, const DevPlan *dP, const BondTables *dT, const double *W,
-                                  uint64_t n_chunks, uint64_t n_tasks, int grid, double *partial, hipStream_t s) {
-#define ISING_BW_NC(TJ)                                                                       \
-  switch (n_classes) {                                                                        \
-    case 1: return launch_bond<TJ, 1>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
-    case 2: return launch_bond<TJ, 2>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
-    case 4: return launch_bond<TJ, 4>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
-    case 8: return launch_bond<TJ, 8>(dP, dT, W, n_chunks, n_tasks, grid, partial, s);        \
-  }                                                                                           \
+                                  uint64_t n_chunks, uint64_t t_begin, uint64_t n_tasks, int mirror, int grid,
+                                  double *partial, hipStream_t s) {
+#define ISING_BW_NC(TJ)                                                                                   \
+  switch (n_classes) {                                                                                    \
+    case 1: return launch_bond<TJ, 1>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
+    case 2: return launch_bond<TJ, 2>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
+    case 4: return launch_bond<TJ, 4>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
+    case 8: return launch_bond<TJ, 8>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
+  }                                                                                                       \
   break;
   switch (tile) {
     case 1: ISING_BW_NC(1)
@@ -506,12 +512,8 @@ static ising_status bond_dispatch(int tile, int n_classes, const DevPlan *dP, co
   return fail(ISING_EUNSUPPORTED, "tile bits or class count out of range");
 }
 
-}  // namespace ising
-
-using namespace ising;
-
-extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev,
-                                            void *workspace, size_t workspace_bytes, void *stream) {
+static ising_status bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev, void *workspace,
+                                  size_t workspace_bytes, bool halve, void *stream) {
   if (!pc) return fail(ISING_EINVAL, "plan is NULL");
   const BondPlan *bp = pc->bond;
   if (bp->status != ISING_OK) return fail(bp->status, bp->error);
@@ -537,13 +539,33 @@ extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *
   static_assert(kBwWaves * kWave == 1 << kLaneBits, "a block walks 2^kLaneBits chunks per task");
   const uint64_t block = uint64_t(kBwWaves) * kWave;
   const uint64_t n_tasks = (n_chunks + block - 1) / block;
-  const int grid = int(std::min<uint64_t>({n_tasks, uint64_t(cus), uint64_t(kMaxBwBlocks)}));
+  // Halving needs the top spin to be a task bit (at least two tasks, both
+  // powers of two): tasks [n_tasks/2, n_tasks) are the configurations with
+  // it up.  Smaller lattices take the full walk, with the same result.
+  const bool mirror = halve && n_tasks >= 2;
+  const uint64_t t_begin = mirror ? n_tasks / 2 : 0;
+  const int grid = int(std::min<uint64_t>({n_tasks - t_begin, uint64_t(cus), uint64_t(kMaxBwBlocks)}));
   hipStream_t s = static_cast<hipStream_t>(stream);
   double *partial = static_cast<double *>(workspace);
-  st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, dP, dT, W_dev, n_chunks, n_tasks, grid, partial, s);
+  st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, dP, dT, W_dev, n_chunks, t_begin, n_tasks, mirror ? 1 : 0,
+                     grid, partial, s);
   if (st != ISING_OK) return st;
   hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(bp->tables.n_pairs)), dim3(kFinishThreads), 0, s, dT, dmap,
                      partial, grid, dJ_dev);
   HIP_TRY(hipGetLastError());
   return ISING_OK;
+}
+
+}  // namespace ising
+
+using namespace ising;
+
+extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev,
+                                            void *workspace, size_t workspace_bytes, void *stream) {
+  return bond_backward(pc, W_dev, dJ_dev, workspace, workspace_bytes, false, stream);
+}
+
+extern "C" ising_status ising_bond_backward_symmetric(const ising_plan *pc, const double *W_dev, double *dJ_dev,
+                                                      void *workspace, size_t workspace_bytes, void *stream) {
+  return bond_backward(pc, W_dev, dJ_dev, workspace, workspace_bytes, true, stream);
 }

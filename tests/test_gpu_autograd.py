@@ -88,8 +88,9 @@ def test_bin_weights_match_oracle(api, name):
     np.testing.assert_allclose(W, ref, rtol=1e-12, atol=1e-15 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
 @pytest.mark.parametrize("name", list(LATS))
-def test_bond_backward_matches_oracle(api, name):
+def test_bond_backward_matches_oracle(api, name, symmetric):
     lat = LATS[name]
     g, gp = _split(name)
     S, N = lat.abs_coupling_sum, lat.n_spins
@@ -99,7 +100,7 @@ def test_bond_backward_matches_oracle(api, name):
     W = rng.standard_normal(g.shape) * np.exp(-rng.uniform(0, 3, g.shape))
     plan = api.Plan(lat)
     print(f"{name}: N={N} tile={plan.tile_bits} bonds={lat.n_bonds}", flush=True)
-    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda(), symmetric=symmetric).cpu().numpy()
     ref = grad.bond_grad_from_weights(g, gp, np.where(g > 0, W, 0.0))
     scale = (np.abs(W) * g.astype(np.float64)).sum()
     np.testing.assert_allclose(dJ, ref, rtol=0, atol=1e-13 * scale)
@@ -128,7 +129,8 @@ def _torus_bond(lat, b):
     return d, u % Lx, u // Lx
 
 
-def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api):
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
+def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api, symmetric):
     # The full 2^40 backward on the +-J 8x5 torus (about 2000 tasks per block),
     # with a random weight table; two bonds of every kind of bit pair, each
     # against the oracle's transfer-matrix split of that bond.
@@ -141,7 +143,7 @@ def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api):
     kinds = _bond_kinds(plan, lat)
     print("8x5 bond kinds:", {k: len(v) for k, v in sorted(kinds.items())}, flush=True)
     assert {"inner-task", "lane-task", "task-task", "inner-inner"} <= set(kinds)
-    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda(), symmetric=symmetric).cpu().numpy()
     scale = (np.abs(W) * g.astype(np.float64)).sum()
     for k in sorted(kinds):
         for b in kinds[k][:2]:
@@ -151,7 +153,8 @@ def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api):
             assert abs(dJ[b] - ref) <= 1e-13 * scale, (k, b, dJ[b], ref, scale)
 
 
-def test_torus6x6_backward_random_weights_equal_on_every_bond(api):
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
+def test_torus6x6_backward_random_weights_equal_on_every_bond(api, symmetric):
     # On the edge-transitive 6x6 torus at uniform J every bond has the same
     # split table, so for any W(E, M) all 72 bond sums agree; one horizontal and
     # one vertical bond are checked against the transfer-matrix split.
@@ -161,7 +164,7 @@ def test_torus6x6_backward_random_weights_equal_on_every_bond(api):
     rng = np.random.default_rng(36)
     W = np.where(g > 0, rng.uniform(-1, 1, g.shape), 0.0)
     plan = api.Plan(lat)
-    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda(), symmetric=symmetric).cpu().numpy()
     scale = (np.abs(W) * g.astype(np.float64)).sum()
     np.testing.assert_allclose(dJ, dJ.mean(), rtol=0, atol=1e-13 * scale)
     for b in (0, 1):
@@ -170,8 +173,9 @@ def test_torus6x6_backward_random_weights_equal_on_every_bond(api):
         assert abs(dJ[b] - ref) <= 1e-13 * scale, (b, dJ[b], ref, scale)
 
 
-@pytest.mark.parametrize("n,mid", [(21, 1), (23, 3), (25, 4), (19, 0)])
-def test_bond_backward_middle_widths(api, n, mid):
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
+@pytest.mark.parametrize("n,mid", [(21, 1), (23, 3), (25, 4), (19, 0), (12, 0)])
+def test_bond_backward_middle_widths(api, n, mid, symmetric):
     # With a 3-bit tile the backward takes mid = min(4, n - 3 - 17) middle bits
     # (fewer on small lattices, to keep 256 tasks), so these sizes cover every
     # middle width, and with it every split of the spins between middle,
@@ -183,7 +187,7 @@ def test_bond_backward_middle_widths(api, n, mid):
     W = np.where(g > 0, rng.standard_normal(g.shape), 0.0)
     plan = api.Plan(lat, api.Tune(tile_bits=3))
     assert plan.tile_bits == 3
-    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda()).cpu().numpy()
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda(), symmetric=symmetric).cpu().numpy()
     ref = grad.bond_grad_from_weights(g, gp, W)
     scale = (np.abs(W) * g.astype(np.float64)).sum()
     np.testing.assert_allclose(dJ, ref, rtol=0, atol=1e-13 * scale)
@@ -339,3 +343,19 @@ def test_torus6x6_bond_gradients_match_kaufman_and_sum_rule(api, ag):
                 with mp.workdps(40):
                     dK = float(mp.diff(lambda Jv: closed_forms.kaufman_logz(6, 6, t / Jv), 1))
                 np.testing.assert_allclose(gJ, dK / lat.n_bonds, rtol=1e-10)
+
+
+def test_symmetric_backward_option_matches_full(ag):
+    # IsingLogZ(symmetric_backward=True) gives the same per-bond gradient as the
+    # full recomputation (+-J cube, random loss weights over a 5 x 3 grid).
+    lat = LATS["cubic3_pm"]
+    T = torch.tensor([0.8, 1.3, 2.0, 3.1, 4.5], dtype=torch.float64, device="cuda")
+    h = torch.tensor([-0.4, 0.0, 0.9], dtype=torch.float64, device="cuda")
+    G = torch.from_numpy(np.random.default_rng(3).standard_normal((5, 3))).cuda()
+    out = []
+    for sym in (False, True):
+        f = ag.IsingLogZ(lat, symmetric_backward=sym)
+        J = f.couplings()
+        (gJ,) = torch.autograd.grad((f(T, h, J) * G).sum(), J)
+        out.append(gJ.cpu().numpy())
+    np.testing.assert_allclose(out[1], out[0], rtol=1e-12, atol=1e-13 * np.abs(out[0]).max())
