@@ -234,7 +234,11 @@ def bench_autograd(plain_rate: float, reps: int) -> dict:
     from paper_1110_2561_amd import autograd as ag
     from paper_1110_2561_amd import lattice as L
     w = L.workload("autograd")
-    out = {"grid": [len(w["T"]), len(w["h"])], "dtype": "f64 sums over u32/u64 enumeration", "lattices": []}
+    out = {"grid": [len(w["T"]), len(w["h"])], "dtype": "f64 sums over u32/u64 enumeration",
+           "backward": "dT, dh from g; per-bond dJ by a recomputed walk over all 2^N configurations",
+           "backward_symmetric": "the same, dJ walking the half with the top spin up with weights "
+                                 "W(E,M) + W(E,-M) (spin-flip symmetry); checked equal to the full form",
+           "lattices": []}
     for lat in w["lattices"]:
         f = ag.IsingLogZ(lat)
         T = torch.as_tensor(w["T"], dtype=torch.float64, device="cuda").requires_grad_(True)
@@ -258,6 +262,14 @@ def bench_autograd(plain_rate: float, reps: int) -> dict:
         assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(rhs)), (lhs, rhs)
         fms = _median_ms(fwd, reps)
         bms = _median_ms(bwd, reps)
+        f.symmetric_backward = True          # the per-bond sums over half the configurations
+        g_full = res["g"]
+        bwd()
+        torch.cuda.synchronize()
+        for a, b in zip(g_full, res["g"]):
+            assert torch.allclose(a, b, rtol=1e-10, atol=1e-12 * float(a.abs().max())), "halved backward differs"
+        sms = _median_ms(bwd, reps)
+        f.symmetric_backward = False
         configs = 1 << lat.n_spins
         out["lattices"].append({
             "lattice": f"{lat.kind} {lat.describe()['dims']} (N={lat.n_spins}, {lat.n_bonds} bonds, "
@@ -267,6 +279,9 @@ def bench_autograd(plain_rate: float, reps: int) -> dict:
             "backward_value": configs / (bms * 1e-3),
             "unit": "configs/s",
             "vs_plain": configs / (bms * 1e-3) / plain_rate,
+            "backward_symmetric_ms": sms,
+            "backward_symmetric_covered": configs / (sms * 1e-3),
+            "symmetric_vs_plain": configs / (sms * 1e-3) / plain_rate,
         })
     return out
 
