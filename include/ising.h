@@ -243,6 +243,13 @@ ising_status ising_batch_layout(const ising_batch_plan *plan, int64_t *offsets, 
  * overwritten), in one persistent launch. */
 ising_status ising_batch_enumerate(const ising_batch_plan *plan, uint64_t *g_all_dev, void *stream);
 
+/* The same tables from half of the configurations (the batched form of
+ * ising_enumerate_symmetric): every member with at least two chunks is
+ * enumerated over the chunks with its top spin up, then mirrored,
+ * g(E, M) = h(E, M) + h(E, -M) (a global spin flip keeps E and negates M).
+ * Bit-identical to ising_batch_enumerate.  Arguments as there. */
+ising_status ising_batch_enumerate_symmetric(const ising_batch_plan *plan, uint64_t *g_all_dev, void *stream);
+
 /* log Z and moments of every member on one (T, h) grid, as ising_moments;
  * each output (any may be NULL) is [n][nT][nh] FP64 on the device. */
 ising_status ising_batch_moments(const ising_batch_plan *plan, const uint64_t *g_all_dev, const double *T_dev,

@@ -74,6 +74,7 @@ ising_batch_plan_create = _sig("ising_batch_plan_create", i32, ctypes.POINTER(is
 ising_batch_plan_destroy = _sig("ising_batch_plan_destroy", i32, vp)
 ising_batch_layout = _sig("ising_batch_layout", i32, vp, i64p, i32p, i32p, i32p, i32p)
 ising_batch_enumerate = _sig("ising_batch_enumerate", i32, vp, vp, vp)
+ising_batch_enumerate_symmetric = _sig("ising_batch_enumerate_symmetric", i32, vp, vp, vp)
 ising_batch_moments = _sig("ising_batch_moments", i32, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp)
 ising_batch_graph_create = _sig("ising_batch_graph_create", i32, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp,
                                 ctypes.POINTER(vp))

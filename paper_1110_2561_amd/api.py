@@ -275,11 +275,15 @@ def _check_all(plan: BatchPlan, g_all: torch.Tensor):
         raise ValueError(f"g_all must be a contiguous CUDA uint64 tensor of {int(plan.offsets[-1])} elements")
 
 
-def batch_enumerate(plan: BatchPlan, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """g(E, M) of every member, concatenated (ising_batch_enumerate)."""
+def batch_enumerate(plan: BatchPlan, out: torch.Tensor | None = None, stream=None,
+                    symmetric: bool = False) -> torch.Tensor:
+    """g(E, M) of every member, concatenated (ising_batch_enumerate); with symmetric,
+    from the half of each member's configurations with its top spin up, mirrored
+    M -> -M (ising_batch_enumerate_symmetric), bit-identical."""
     g = plan.new_tables() if out is None else out
     _check_all(plan, g)
-    _lib.check(_lib.ising_batch_enumerate(plan.handle, g.data_ptr(), _stream_handle(stream)))
+    fn = _lib.ising_batch_enumerate_symmetric if symmetric else _lib.ising_batch_enumerate
+    _lib.check(fn(plan.handle, g.data_ptr(), _stream_handle(stream)))
     return g
 
 

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(1024) void k_batch_enumerate(const DevPlan *__restr
     }
     const DevPlan *P = &plans[cur];
     const uint64_t chunk = un.task * blockDim.x + offset;
-    if (chunk < meta[cur].n_chunks) {
+    if (chunk < meta[cur].n_chunks && offset >= uint32_t(un.first_offset)) {
       const uint32_t rep = lane_copy(lane, P->R);
       switch (P->tile) {  // uniform: each member keeps its own tile width
         case 1: walk_chunk<1, NC>(st, chunk, rep, hist); break;
@@ -108,26 +108,49 @@ static ising_status batch_device(ising_batch_plan *bp, int device, ising_batch_p
     HIP_TRY(hipMalloc(&d.plans, sizeof(DevPlan) * plans.size()));
     HIP_TRY(hipMalloc(&d.meta, sizeof(BatchMember) * bp->meta.size()));
     HIP_TRY(hipMalloc(&d.units, sizeof(BatchUnit) * std::max<size_t>(1, bp->units.size())));
+    HIP_TRY(hipMalloc(&d.units_half, sizeof(BatchUnit) * std::max<size_t>(1, bp->units_half.size())));
     HIP_TRY(hipMalloc(&d.counter, sizeof(uint32_t)));
     HIP_TRY(hipMemcpy(d.plans, plans.data(), sizeof(DevPlan) * plans.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.meta, bp->meta.data(), sizeof(BatchMember) * bp->meta.size(), hipMemcpyHostToDevice));
     if (!bp->units.empty())
       HIP_TRY(hipMemcpy(d.units, bp->units.data(), sizeof(BatchUnit) * bp->units.size(), hipMemcpyHostToDevice));
+    if (!bp->units_half.empty())
+      HIP_TRY(hipMemcpy(d.units_half, bp->units_half.data(), sizeof(BatchUnit) * bp->units_half.size(),
+                        hipMemcpyHostToDevice));
   }
   *out = &d;
   return ISING_OK;
 }
 
 template <int NC>
-static void launch_batch_nc(const ising_batch_plan::Dev *d, uint32_t n_units, int grid, int block,
-                            unsigned long long *g, hipStream_t s) {
+static void launch_batch_nc(const ising_batch_plan::Dev *d, const void *units, uint32_t n_units, int grid,
+                            int block, unsigned long long *g, hipStream_t s) {
   hipLaunchKernelGGL((k_batch_enumerate<NC>), dim3(grid), dim3(block), 0, s,
                      static_cast<const DevPlan *>(d->plans), static_cast<const BatchMember *>(d->meta),
-                     static_cast<const BatchUnit *>(d->units), n_units, static_cast<uint32_t *>(d->counter), g);
+                     static_cast<const BatchUnit *>(units), n_units, static_cast<uint32_t *>(d->counter), g);
+}
+
+// Halved run: every member with at least two chunks was enumerated over the
+// chunks with its top spin up; g(E, M) = h(E, M) + h(E, -M) restores it
+// (a global flip keeps E and negates M).  One block row per member.
+__global__ void k_batch_mirror(const BatchMember *__restrict__ meta, unsigned long long *__restrict__ g_all) {
+  const BatchMember m = meta[blockIdx.y];
+  if (m.n_chunks < 2) return;
+  unsigned long long *g = g_all + m.offset;
+  const int half = (m.n_m + 1) / 2;   // nu in [0, half) pairs with n_m - 1 - nu
+  const size_t cells = size_t(m.n_e) * half;
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < cells; i += size_t(gridDim.x) * blockDim.x) {
+    const size_t e = i / half;
+    const int nu = int(i - e * half), mu = m.n_m - 1 - nu;
+    unsigned long long *row = g + e * m.n_m;
+    const unsigned long long v = row[nu] + row[mu];
+    row[nu] = v;
+    row[mu] = v;
+  }
 }
 
 static ising_status batch_enumerate_launch(const ising_batch_plan *bpc, uint64_t *g_all, hipStream_t s,
-                                           const ising_batch_plan::Dev *d) {
+                                           const ising_batch_plan::Dev *d, bool halve = false) {
   const ising_batch_plan *bp = bpc;
   int dev = 0, cus = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -138,20 +161,26 @@ static ising_status batch_enumerate_launch(const ising_batch_plan *bpc, uint64_t
   hipLaunchKernelGGL(k_batch_prepare, dim3(unsigned(fill_blocks)), dim3(256), 0, s, g, n_elems,
                      static_cast<uint32_t *>(d->counter));
   HIP_TRY(hipGetLastError());
-  const uint32_t n_units = uint32_t(bp->units.size());
+  const uint32_t n_units = uint32_t((halve ? bp->units_half : bp->units).size());
+  const void *units = halve ? d->units_half : d->units;
   if (!n_units) return ISING_OK;
   int grid = cus;
   if (bp->max_blocks > 0 && bp->max_blocks < grid) grid = bp->max_blocks;
   if (uint32_t(grid) > n_units) grid = int(n_units);
   const int block = kWave * bp->waves_per_block;
-switch (bp->n_classes) {
-    case 1: launch_batch_nc<1>(d, n_units, grid, block, g, s); break;
-    case 2: launch_batch_nc<2>(d, n_units, grid, block, g, s); break;
-    case 4: launch_batch_nc<4>(d, n_units, grid, block, g, s); break;
-    case 8: launch_batch_nc<8>(d, n_units, grid, block, g, s); break;
+  switch (bp->n_classes) {
+    case 1: launch_batch_nc<1>(d, units, n_units, grid, block, g, s); break;
+    case 2: launch_batch_nc<2>(d, units, n_units, grid, block, g, s); break;
+    case 4: launch_batch_nc<4>(d, units, n_units, grid, block, g, s); break;
+    case 8: launch_batch_nc<8>(d, units, n_units, grid, block, g, s); break;
     default: return fail(ISING_EUNSUPPORTED, "class count");
   }
   HIP_TRY(hipGetLastError());
+  if (halve) {
+    hipLaunchKernelGGL(k_batch_mirror, dim3(16, unsigned(bp->n)), dim3(256), 0, s,
+                       static_cast<const BatchMember *>(d->meta), g);
+    HIP_TRY(hipGetLastError());
+  }
   return ISING_OK;
 }
 
@@ -235,8 +264,18 @@ extern "C" ising_status ising_batch_plan_create(const ising_lattice *lats, int32
                    [&](int a, int b) { return bp->members[a]->n_spins > bp->members[b]->n_spins; });
   const uint64_t block = uint64_t(kWave) * bp->waves_per_block;
   for (int i : order) {
-    const uint64_t tasks = (bp->meta[i].n_chunks + block - 1) / block;
+    const uint64_t nc = bp->meta[i].n_chunks;
+    const uint64_t tasks = (nc + block - 1) / block;
     for (uint64_t t = 0; t < tasks; ++t) bp->units.push_back(BatchUnit{i, 0, t});
+    // Halved list: chunks [nc/2, nc), whose top chunk bit (the top spin) is
+    // up (nc is a power of two); a one-chunk member runs whole.
+    if (nc < 2) {
+      bp->units_half.push_back(BatchUnit{i, 0, 0});
+    } else {
+      const uint64_t h0 = nc / 2, t0 = h0 / block;
+      for (uint64_t t = t0; t < tasks; ++t)
+        bp->units_half.push_back(BatchUnit{i, t == t0 ? int32_t(h0 - t0 * block) : 0, t});
+    }
   }
   if (bp->units.size() >= (size_t(1) << 31)) {
     ising_batch_plan_destroy(bp);
@@ -255,6 +294,7 @@ extern "C" ising_status ising_batch_plan_destroy(ising_batch_plan *bp) {
     if (x.plans) (void)hipFree(x.plans);
     if (x.meta) (void)hipFree(x.meta);
     if (x.units) (void)hipFree(x.units);
+    if (x.units_half) (void)hipFree(x.units_half);
     if (x.counter) (void)hipFree(x.counter);
   }
   delete bp;
@@ -284,6 +324,17 @@ extern "C" ising_status ising_batch_enumerate(const ising_batch_plan *bp, uint64
   ising_status st = batch_device(const_cast<ising_batch_plan *>(bp), dev, &d);
   if (st != ISING_OK) return st;
   return batch_enumerate_launch(bp, g_all_dev, static_cast<hipStream_t>(stream), d);
+}
+
+extern "C" ising_status ising_batch_enumerate_symmetric(const ising_batch_plan *bp, uint64_t *g_all_dev,
+                                                        void *stream) {
+  if (!bp || !g_all_dev) return fail(ISING_EINVAL, "batch plan or g_all_dev is NULL");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  ising_batch_plan::Dev *d = nullptr;
+  ising_status st = batch_device(const_cast<ising_batch_plan *>(bp), dev, &d);
+  if (st != ISING_OK) return st;
+  return batch_enumerate_launch(bp, g_all_dev, static_cast<hipStream_t>(stream), d, true);
 }
 
 extern "C" ising_status ising_batch_moments(const ising_batch_plan *bp, const uint64_t *g_all_dev,

@@ -80,10 +80,12 @@ struct ising_plan {
 
 namespace ising {
 
-// One unit of batched work: task `task` (chunks task*block .. +block) of member `inst`.
+// One unit of batched work: task `task` (chunks task*block .. +block) of member
+// `inst`; chunks whose offset in the task is below first_offset are skipped
+// (the lower half of a one-task member in a halved run).
 struct BatchUnit {
   int32_t inst;
-  int32_t pad;
+  int32_t first_offset;
   uint64_t task;
 };
 
@@ -122,12 +124,14 @@ struct ising_batch_plan {
   std::vector<ising_plan *> members;      // owned
   std::vector<ising::BatchMember> meta;
   std::vector<ising::BatchUnit> units;
+  std::vector<ising::BatchUnit> units_half;   // halved run: chunks with the top spin up
   int64_t total_elems = 0;
   std::mutex mu;
   struct Dev {
     void *plans = nullptr;    // DevPlan[n]
     void *meta = nullptr;     // BatchMember[n]
     void *units = nullptr;    // BatchUnit[units]
+    void *units_half = nullptr;  // BatchUnit[units_half]
     void *counter = nullptr;  // uint32 work counter
   } dev[ising::kMaxDevices];
 };

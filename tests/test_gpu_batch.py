@@ -46,10 +46,12 @@ def small_batch():
 @pytest.mark.parametrize("tune", [None, {"prefix_bits": 4}, {"prefix_bits": 12, "replicas": 4},
                                   {"max_blocks": 3, "waves_per_block": 4}, {"tile_bits": 2}],
                          ids=["default", "pb4", "pb12-r4", "3blocks", "tile2"])
-def test_small_batch_bit_exact(api, tune):
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
+def test_small_batch_bit_exact(api, tune, symmetric):
     lats = small_batch()
     plan = api.BatchPlan(lats, api.Tune(**tune) if tune else None)
-    g = api.batch_enumerate(plan)
+    stale = torch.full((int(plan.offsets[-1]),), 12345, dtype=torch.int64, device="cuda").view(torch.uint64)
+    g = api.batch_enumerate(plan, out=stale, symmetric=symmetric)
     torch.cuda.synchronize()
     g_host = g.cpu()
     for i, lat in enumerate(lats):
@@ -79,6 +81,16 @@ def test_batch256_parity(api):
         elif i in tri_small or i in cubes:
             print(f"member {i}: {lat.kind} N={N} vs brute force", flush=True)
             np.testing.assert_array_equal(t, _bf(lat))
+
+
+def test_batch256_halved_equals_full(api):
+    # every member with two or more chunks walks only its configurations with
+    # the top spin up, then mirrors: the tables are identical to the full run
+    lats = L.workload("batch256")["lattices"]
+    plan = api.BatchPlan(lats)
+    full = api.batch_enumerate(plan).cpu()
+    half = api.batch_enumerate(plan, symmetric=True).cpu()
+    assert torch.equal(full, half)
 
 
 def test_batch_matches_single_lattice_path(api):
