@@ -38,7 +38,7 @@ COUNTERS = {
     # rocprofv3 counters of k_enumerate on the 6x6 torus (profiles/k_enumerate_torus6x6_*.txt),
     # valid while the kernel's sources hash to sha256.
     "sources": ['paper_1110_2561_amd/csrc/enumerate.hip', 'paper_1110_2561_amd/csrc/walk.h', 'paper_1110_2561_amd/csrc/plan.cpp', 'paper_1110_2561_amd/csrc/internal.h'],
-    "sha256": "0684bdfbe1b9ca1900f3d9cc53c9419c4e16c0ed6f8aa3dffcc4e5f76313d1a0",
+    "sha256": "636331100238d52aed75f9868a462aa8e883f70c3b705cb13f9d086a7d6a64cb",
     "workload": "torus6x6",
     # FETCH_SIZE 81.0 KiB x 2.0 + WRITE_SIZE 936.28 KiB x 1.0 per launch; the
     # factors are what a 512 MiB copy kernel reads on the same counters.
