@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -193,6 +194,12 @@ struct ising_graph {
   hipGraphExec_t exec = nullptr;
 };
 
+// Tail of the batch work list: a task is one chunk per thread of a
+// 1024-thread block (2^10 chunks); kTailBlocks is the CU count of an MI355X.
+constexpr int kTailTaskBits = 10;
+constexpr int kTailBlocks = 256;
+constexpr int kTailInner = 12;
+
 extern "C" ising_status ising_batch_plan_create(const ising_lattice *lats, int32_t n, const ising_tune *tune,
                                                 ising_batch_plan **out) {
   if (!out) return fail(ISING_EINVAL, "plan output pointer is NULL");
@@ -207,9 +214,29 @@ extern "C" ising_status ising_batch_plan_create(const ising_lattice *lats, int32
   // Pass 1: each member on its own, to find the largest class count (one
   // kernel instantiation serves the batch; members keep their own tile width,
   // capped by tune.tile_bits when given).
+  // The smallest members, together about one round of units over the grid
+  // (kTailBlocks tasks of the default width) and last in the longest-first
+  // work list, take short chunks (at most 2^kTailInner configurations), so
+  // the launch ends on short units and blocks finish closer together.
+  std::vector<char> tail(size_t(n), 0);
+  if (inner_default > 2) {
+    std::vector<int> by_size(static_cast<size_t>(n));
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::stable_sort(by_size.begin(), by_size.end(),
+                     [&](int a, int b) { return lats[a].n_spins < lats[b].n_spins; });
+    const double budget = double(kTailBlocks) * std::ldexp(1.0, inner_default + kTailTaskBits);
+    double cum = 0.0;
+    for (int i : by_size) {
+      cum += std::ldexp(1.0, std::max(0, std::min(lats[i].n_spins, 63)));
+      if (cum > budget) break;
+      tail[size_t(i)] = 1;
+    }
+  }
   auto member_tune = [&](int i) {
     ising_tune t = tn;
-    t.inner_bits = inner_default ? std::min(inner_default, lats[i].n_spins) : 0;
+    int inner = inner_default;
+    if (tail[size_t(i)]) inner = std::min(inner - 2, kTailInner);
+    t.inner_bits = inner ? std::min(inner, lats[i].n_spins) : 0;
     if (t.inner_bits && !t.tile_bits) t.tile_bits = std::min(kMaxTile, t.inner_bits);
     return t;
   };

@@ -167,11 +167,16 @@ __device__ inline void walk_chunk(const SiteTable<NC> &st, uint64_t chunk, uint3
 __device__ inline void flush_hist(const DevPlan *__restrict__ P, uint32_t *h, unsigned long long *__restrict__ g) {
   const int W = P->W, R = P->R;
   const int bins = P->n_ec * W;
+  // Lane b of a half-wave visits the copies of bin b starting at copy
+  // (b mod 32) / (32 / R): the 32 words it touches at each step then lie in
+  // 32 different banks (in copy order they would share 32 / R banks).
+  const int rot = (int(threadIdx.x) & 31) / (32 / R);
   for (int b = threadIdx.x; b < bins; b += blockDim.x) {
     unsigned long long s = 0;
     for (int r = 0; r < R; ++r) {
-      s += h[b * R + r];
-      h[b * R + r] = 0;
+      const int w = b * R + ((r + rot) & (R - 1));
+      s += h[w];
+      h[w] = 0;
     }
     const int e_idx = b / W, nu = b - e_idx * W;
     if (s && nu < P->n_m) {
