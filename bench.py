@@ -38,15 +38,15 @@ COUNTERS = {
     # rocprofv3 counters of k_enumerate on the 6x6 torus (profiles/k_enumerate_torus6x6_*.txt),
     # valid while the kernel's sources hash to sha256.
     "sources": ['paper_1110_2561_amd/csrc/enumerate.hip', 'paper_1110_2561_amd/csrc/walk.h', 'paper_1110_2561_amd/csrc/plan.cpp', 'paper_1110_2561_amd/csrc/internal.h'],
-    "sha256": "636331100238d52aed75f9868a462aa8e883f70c3b705cb13f9d086a7d6a64cb",
+    "sha256": "0ee52cfb0a44b48835888db5caab1e85a40135e04ba9ead95b4bbbae0ddae7d1",
     "workload": "torus6x6",
-    # FETCH_SIZE 81.0 KiB x 2.0 + WRITE_SIZE 936.28 KiB x 1.0 per launch; the
+    # FETCH_SIZE 85.0 KiB x 2.0 + WRITE_SIZE 936.28 KiB x 1.0 per launch; the
     # factors are what a 512 MiB copy kernel reads on the same counters.
-    "hbm_bytes_per_launch": int((81.0 * 2.0 + 936.28125 * 1.0) * 1024),
+    "hbm_bytes_per_launch": int((85.0 * 2.0 + 936.28125 * 1.0) * 1024),
     # SQ_INSTS_VALU_INT32 x 64 lanes / 2^36 configurations
-    "int32_valu_per_config": 1132903146 * 64 / 2 ** 36,
+    "int32_valu_per_config": 1133076202 * 64 / 2 ** 36,
     # SQ_INSTS_VALU x 64 lanes / 2^36 configurations (all VALU)
-    "valu_per_config": 1210544730 * 64 / 2 ** 36,
+    "valu_per_config": 1210787418 * 64 / 2 ** 36,
 }
 
 
