@@ -163,6 +163,11 @@ def bench_batched(plain_rate: float, reps: int) -> dict:
     graph.replay()
     torch.cuda.synchronize()
     gms = _median_ms(graph.replay, reps)
+    hgraph = api.BatchGraph(plan, w["T"], w["h"], symmetric=True)
+    hgraph.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(hgraph.g_all.cpu(), g_host), "halved graph differs from the full batch"
+    hgms = _median_ms(hgraph.replay, reps)
     kinds = sorted({lat.kind for lat in plan.lattices})
     return {
         "workload": f"batch256: {len(plan)} lattices ({', '.join(kinds)}), N in "
@@ -175,6 +180,7 @@ def bench_batched(plain_rate: float, reps: int) -> dict:
         "graph": f"zero + batched enumerate + batched moments on {len(w['T'])} T x {len(w['h'])} h",
         "vs_plain": total / (ms * 1e-3) / plain_rate,
         "halved_ms": hms,
+        "halved_graph_ms": hgms,
         "halved_covered": total / (hms * 1e-3),
         "halved": "each member over its configurations with the top spin up, then g(E,M) += g(E,-M); "
                   "checked bit-identical to the full batch",

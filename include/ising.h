@@ -265,6 +265,11 @@ ising_status ising_batch_graph_create(const ising_batch_plan *plan, uint64_t *g_
                                       int32_t nT, const double *h_dev, int32_t nh, double *logz_dev,
                                       double *mean_E, double *mean_M, double *heat_capacity,
                                       double *susceptibility, ising_graph **graph);
+/* The same graph with the halved enumeration (ising_batch_enumerate_symmetric). */
+ising_status ising_batch_graph_create_symmetric(const ising_batch_plan *plan, uint64_t *g_all_dev,
+                                                const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
+                                                double *logz_dev, double *mean_E, double *mean_M,
+                                                double *heat_capacity, double *susceptibility, ising_graph **graph);
 ising_status ising_graph_launch(const ising_graph *graph, void *stream);
 ising_status ising_graph_destroy(ising_graph *graph);
 

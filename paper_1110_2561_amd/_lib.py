@@ -78,6 +78,8 @@ ising_batch_enumerate_symmetric = _sig("ising_batch_enumerate_symmetric", i32, v
 ising_batch_moments = _sig("ising_batch_moments", i32, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp)
 ising_batch_graph_create = _sig("ising_batch_graph_create", i32, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp,
                                 ctypes.POINTER(vp))
+ising_batch_graph_create_symmetric = _sig("ising_batch_graph_create_symmetric", i32, vp, vp, vp, i32, vp, i32, vp,
+                                          vp, vp, vp, vp, ctypes.POINTER(vp))
 ising_graph_launch = _sig("ising_graph_launch", i32, vp, vp)
 ising_graph_destroy = _sig("ising_graph_destroy", i32, vp)
 ising_status_str = _sig("ising_status_str", ctypes.c_char_p, i32)

@@ -307,20 +307,20 @@ def batch_moments(plan: BatchPlan, g_all: torch.Tensor, T, h, stream=None) -> di
 
 class BatchGraph:
     """A HIP graph of {zero, batched enumeration, batched moments} with its
-    buffers (ising_batch_graph_create); replay() launches it."""
+    buffers (ising_batch_graph_create); replay() launches it.  With symmetric
+    the enumeration is the halved one (ising_batch_graph_create_symmetric)."""
 
-    def __init__(self, plan: BatchPlan, T, h, device="cuda"):
+    def __init__(self, plan: BatchPlan, T, h, device="cuda", symmetric: bool = False):
         self.plan = plan
         self.g_all = plan.new_tables(device)
         self.T, self.h = _grid(T, device), _grid(h, device)
         self.outs = _batch_outputs(plan, self.T, self.h, device)
         handle = ctypes.c_void_p()
         o = self.outs
-        _lib.check(_lib.ising_batch_graph_create(plan.handle, self.g_all.data_ptr(), self.T.data_ptr(),
-                                                 self.T.numel(), self.h.data_ptr(), self.h.numel(),
-                                                 o["log_z"].data_ptr(), o["mean_E"].data_ptr(),
-                                                 o["mean_M"].data_ptr(), o["heat_capacity"].data_ptr(),
-                                                 o["susceptibility"].data_ptr(), ctypes.byref(handle)))
+        fn = _lib.ising_batch_graph_create_symmetric if symmetric else _lib.ising_batch_graph_create
+        _lib.check(fn(plan.handle, self.g_all.data_ptr(), self.T.data_ptr(), self.T.numel(), self.h.data_ptr(),
+                      self.h.numel(), o["log_z"].data_ptr(), o["mean_E"].data_ptr(), o["mean_M"].data_ptr(),
+                      o["heat_capacity"].data_ptr(), o["susceptibility"].data_ptr(), ctypes.byref(handle)))
         self._h = handle
 
     def replay(self, stream=None):

@@ -380,10 +380,9 @@ extern "C" ising_status ising_batch_moments(const ising_batch_plan *bp, const ui
                              logz, mean_E, mean_M, heat, susc, static_cast<hipStream_t>(stream));
 }
 
-extern "C" ising_status ising_batch_graph_create(const ising_batch_plan *bp, uint64_t *g_all_dev,
-                                                 const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
-                                                 double *logz, double *mean_E, double *mean_M, double *heat,
-                                                 double *susc, ising_graph **out) {
+static ising_status batch_graph_create(const ising_batch_plan *bp, uint64_t *g_all_dev, const double *T_dev,
+                                       int32_t nT, const double *h_dev, int32_t nh, double *logz, double *mean_E,
+                                       double *mean_M, double *heat, double *susc, bool halve, ising_graph **out) {
   if (!out) return fail(ISING_EINVAL, "graph output pointer is NULL");
   *out = nullptr;
   if (!bp || !g_all_dev) return fail(ISING_EINVAL, "batch plan or g_all_dev is NULL");
@@ -403,7 +402,7 @@ extern "C" ising_status ising_batch_graph_create(const ising_batch_plan *bp, uin
   }
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    st = batch_enumerate_launch(bp, g_all_dev, s, d);
+    st = batch_enumerate_launch(bp, g_all_dev, s, d, halve);
     if (st == ISING_OK && nT > 0 && nh > 0 && (logz || mean_E || mean_M || heat || susc))
       st = batch_thermo_launch(static_cast<const BatchMember *>(d->meta), bp->n, g_all_dev, T_dev, nT, h_dev, nh,
                                logz, mean_E, mean_M, heat, susc, s);
@@ -426,6 +425,20 @@ extern "C" ising_status ising_batch_graph_create(const ising_batch_plan *bp, uin
   }
   *out = gr;
   return ISING_OK;
+}
+
+extern "C" ising_status ising_batch_graph_create(const ising_batch_plan *bp, uint64_t *g_all_dev,
+                                                 const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
+                                                 double *logz, double *mean_E, double *mean_M, double *heat,
+                                                 double *susc, ising_graph **out) {
+  return batch_graph_create(bp, g_all_dev, T_dev, nT, h_dev, nh, logz, mean_E, mean_M, heat, susc, false, out);
+}
+
+extern "C" ising_status ising_batch_graph_create_symmetric(const ising_batch_plan *bp, uint64_t *g_all_dev,
+                                                           const double *T_dev, int32_t nT, const double *h_dev,
+                                                           int32_t nh, double *logz, double *mean_E, double *mean_M,
+                                                           double *heat, double *susc, ising_graph **out) {
+  return batch_graph_create(bp, g_all_dev, T_dev, nT, h_dev, nh, logz, mean_E, mean_M, heat, susc, true, out);
 }
 
 extern "C" ising_status ising_graph_launch(const ising_graph *gr, void *stream) {

@@ -125,7 +125,8 @@ def test_batch_moments_match_oracle(api):
         np.testing.assert_allclose(out["susceptibility"][i].cpu().numpy(), chi, rtol=1e-11, atol=1e-300)
 
 
-def test_graph_replays_equal_eager(api):
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
+def test_graph_replays_equal_eager(api, symmetric):
     lats = L.workload("batch256")["lattices"]
     plan = api.BatchPlan(lats)
     T = np.linspace(0.5, 5.0, 64)
@@ -133,7 +134,7 @@ def test_graph_replays_equal_eager(api):
     eager_g = api.batch_enumerate(plan)
     eager = api.batch_moments(plan, eager_g, T, h)
     torch.cuda.synchronize()
-    graph = api.BatchGraph(plan, T, h)
+    graph = api.BatchGraph(plan, T, h, symmetric=symmetric)
     for rep in range(3):
         graph.g_all.fill_(7)                       # stale contents must be overwritten
         for v in graph.outs.values():
