@@ -161,6 +161,18 @@ def test_checkpoint_and_resume(api, tmp_path):
     np.testing.assert_array_equal(resumed.cpu().numpy(), whole)
 
 
+@pytest.mark.parametrize("which", [1, 2], ids=["cubic3", "cubic3_pm"])
+def test_autograd_workload_cubes_bit_exact(api, which):
+    """The autograd workload's 3x3x3 cubes (J = 1 and seeded +-J, 2^27
+    configurations each), plain and halved, against the brute force."""
+    lat = L.workload("autograd")["lattices"][which]
+    assert lat.kind == "cubic_torus" and lat.n_spins == 27
+    ref = native.count_all(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J)
+    plan = api.Plan(lat)
+    np.testing.assert_array_equal(api.enumerate_g(plan).cpu().numpy(), ref)
+    np.testing.assert_array_equal(api.enumerate_symmetric(plan).cpu().numpy(), ref)
+
+
 def test_checkpoint_runner_resumes(api, tmp_path):
     """The library's checkpointed runner on the GPU: stopped after two pieces,
     resumed by a fresh plan, equal to the transfer-matrix table (8x5 +-J)."""
