@@ -94,7 +94,8 @@ def test_batch256_halved_equals_full(api):
 
 
 def test_batch_matches_single_lattice_path(api):
-    lats = L.workload("batch256")["lattices"][::7]
+    # every member of batch256 equals its own single-lattice run
+    lats = L.workload("batch256")["lattices"]
     plan = api.BatchPlan(lats)
     g = api.batch_enumerate(plan).cpu()
     for i, lat in enumerate(lats):
