@@ -128,6 +128,18 @@ def enumerate_range(plan: Plan, first_chunk: int, n_chunks: int, g: torch.Tensor
     return g
 
 
+def _check_dense(g: torch.Tensor):
+    if not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.uint64 and g.dim() == 2
+            and g.is_contiguous()):
+        raise ValueError("g must be a contiguous 2-D CUDA uint64 table [n_e, n_m]")
+
+
+def _check_out(t: torch.Tensor, shape: tuple, device, name: str):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and tuple(t.shape) == tuple(shape) and t.device == device):
+        raise ValueError(f"{name} must be a contiguous float64 tensor of shape {tuple(shape)} on {device}")
+
+
 def _grid(x, device) -> torch.Tensor:
     if isinstance(x, torch.Tensor):
         return x.to(device=device, dtype=torch.float64).reshape(-1).contiguous()
@@ -136,6 +148,7 @@ def _grid(x, device) -> torch.Tensor:
 
 def log_z(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> torch.Tensor:
     """log Z [len(T), len(h)] in FP64 from a dense device table (ising_logz)."""
+    _check_dense(g)
     Tt, ht = _grid(T, g.device), _grid(h, g.device)
     out = torch.empty((Tt.numel(), ht.numel()), dtype=torch.float64, device=g.device)
     n_e, n_m = g.shape
@@ -146,6 +159,7 @@ def log_z(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> torch
 
 def moments(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dict:
     """log Z, <E>, <M>, C = Var(E - hM)/T^2, chi = Var(M)/T, each [len(T), len(h)]."""
+    _check_dense(g)
     Tt, ht = _grid(T, g.device), _grid(h, g.device)
     shape = (Tt.numel(), ht.numel())
     outs = {k: torch.empty(shape, dtype=torch.float64, device=g.device)
@@ -161,6 +175,7 @@ def moments(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dic
 def logz_derivatives(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dict:
     """log Z and its first and second derivatives in (T, h), each [len(T), len(h)]
     (ising_logz_derivatives): keys log_z, d_T, d_h, d_TT, d_Th, d_hh."""
+    _check_dense(g)
     Tt, ht = _grid(T, g.device), _grid(h, g.device)
     shape = (Tt.numel(), ht.numel())
     keys = ("log_z", "d_T", "d_h", "d_TT", "d_Th", "d_hh")
@@ -175,13 +190,15 @@ def logz_derivatives(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=Non
 def bin_weights(g: torch.Tensor, e_min: int, n_spins: int, T, h, logz: torch.Tensor, grad: torch.Tensor,
                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Per-configuration weights W[n_e, n_m] of the loss sum(grad * log Z) (ising_bin_weights)."""
+    _check_dense(g)
     Tt, ht = _grid(T, g.device), _grid(h, g.device)
     shape = (Tt.numel(), ht.numel())
-    lz = logz.to(dtype=torch.float64).contiguous()
+    lz = logz.to(device=g.device, dtype=torch.float64).contiguous()
     gr = grad.to(device=g.device, dtype=torch.float64).contiguous()
     if tuple(lz.shape) != shape or tuple(gr.shape) != shape:
         raise ValueError(f"logz and grad must have shape {shape}")
     W = torch.empty(tuple(g.shape), dtype=torch.float64, device=g.device) if out is None else out
+    _check_out(W, tuple(g.shape), g.device, "out")
     n_e, n_m = g.shape
     _lib.check(_lib.ising_bin_weights(g.data_ptr(), n_e, n_m, int(e_min), int(n_spins), Tt.data_ptr(), Tt.numel(),
                                       ht.data_ptr(), ht.numel(), lz.data_ptr(), gr.data_ptr(), W.data_ptr(),
@@ -198,6 +215,7 @@ def bond_backward(plan: Plan, W: torch.Tensor, out: torch.Tensor | None = None, 
         raise ValueError(f"W must be a contiguous CUDA float64 tensor of shape {(plan.n_e, plan.n_m)}")
     nb = plan.lattice.n_bonds
     dJ = torch.empty(nb, dtype=torch.float64, device=W.device) if out is None else out
+    _check_out(dJ, (nb,), W.device, "out")
     ws = torch.empty(max(plan.bond_workspace_bytes, 8), dtype=torch.uint8, device=W.device)
     fn = _lib.ising_bond_backward_symmetric if symmetric else _lib.ising_bond_backward
     _lib.check(fn(plan.handle, W.data_ptr(), dJ.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))

@@ -145,3 +145,24 @@ def test_batch_plan_errors_name_the_member():
         BatchPlan([])
     with pytest.raises(IsingError, match="member 1"):
         BatchPlan([L.ring(5), L.Lattice(3, [0], [0], [1])])
+
+
+def test_wrappers_reject_tables_a_kernel_cannot_read():
+    # host, non-contiguous, wrongly typed or shaped tensors are refused in
+    # Python, before any pointer reaches the library
+    import torch
+
+    from paper_1110_2561_amd import api
+    from paper_1110_2561_amd import lattice as L
+    g_host = torch.zeros((33, 17), dtype=torch.uint64)
+    for fn in (api.log_z, api.moments, api.logz_derivatives):
+        with pytest.raises(ValueError):
+            fn(g_host, -32, 16, [1.0], [0.0])
+    with pytest.raises(ValueError):
+        api.bin_weights(g_host, -32, 16, [1.0], [0.0], torch.zeros((1, 1), dtype=torch.float64),
+                        torch.zeros((1, 1), dtype=torch.float64))
+    plan = api.Plan(L.square_torus(4, 4))
+    with pytest.raises(ValueError):
+        api.bond_backward(plan, torch.zeros((plan.n_e, plan.n_m), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        api.enumerate_g(plan, out=torch.zeros((plan.n_e, plan.n_m), dtype=torch.uint64))

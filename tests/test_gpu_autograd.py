@@ -222,6 +222,22 @@ def test_bond_backward_edge_cases(api):
     W = np.arange(g.size, dtype=np.float64).reshape(g.shape)
     dJ = api.bond_backward(api.Plan(lat), torch.from_numpy(W).cuda()).cpu().numpy()
     np.testing.assert_allclose(dJ, grad.bond_grad_from_weights(g, gp, np.where(g > 0, W, 0.0)), rtol=1e-15)
+    # outputs of the wrong size, type or layout are refused before any launch
+    plan = api.Plan(L.square_torus(4, 4))
+    Wd = torch.zeros((plan.n_e, plan.n_m), dtype=torch.float64, device="cuda")
+    for bad in (torch.zeros(31, dtype=torch.float64, device="cuda"),
+                torch.zeros(32, dtype=torch.float32, device="cuda"),
+                torch.zeros(64, dtype=torch.float64, device="cuda")[::2]):
+        with pytest.raises(ValueError):
+            api.bond_backward(plan, Wd, out=bad)
+    gt = api.enumerate_g(plan)
+    lz = api.log_z(gt, plan.e_min, 16, [1.0, 2.0], [0.0])
+    G = torch.ones_like(lz)
+    with pytest.raises(ValueError):
+        api.bin_weights(gt, plan.e_min, 16, [1.0, 2.0], [0.0], lz, G,
+                        out=torch.zeros((plan.n_e, plan.n_m - 1), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        api.log_z(gt.t(), plan.e_min, 16, [1.0], [0.0])        # not contiguous
 
 
 # --------------------------------------------------------------------------
