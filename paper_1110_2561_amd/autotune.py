@@ -38,6 +38,15 @@ def cache_path() -> str:
         os.path.expanduser("~"), ".cache", "paper_1110_2561_amd", "autotune.json")
 
 
+def _library_tag() -> str:
+    """Hash of the loaded library file: a rebuilt kernel invalidates cached choices."""
+    from . import _lib
+    h = hashlib.sha256()
+    with open(_lib.LIB_PATH, "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:12]
+
+
 def batch_key(lattices) -> str:
     h = hashlib.sha256()
     for lat in lattices:
@@ -45,7 +54,7 @@ def batch_key(lattices) -> str:
         for a in (lat.bond_i, lat.bond_j, lat.bond_J):
             h.update(np.ascontiguousarray(a, dtype=np.int32).tobytes())
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
-    return f"{arch}:{h.hexdigest()[:24]}"
+    return f"{arch}:{_library_tag()}:{h.hexdigest()[:24]}"
 
 
 def _time_batch(plan: api.BatchPlan, reps: int) -> float:

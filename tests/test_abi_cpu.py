@@ -166,3 +166,12 @@ def test_wrappers_reject_tables_a_kernel_cannot_read():
         api.bond_backward(plan, torch.zeros((plan.n_e, plan.n_m), dtype=torch.float64))
     with pytest.raises(ValueError):
         api.enumerate_g(plan, out=torch.zeros((plan.n_e, plan.n_m), dtype=torch.uint64))
+
+
+def test_autotune_cache_key_names_the_batch_and_the_build():
+    from paper_1110_2561_amd import autotune
+    a = [L.square_torus(4, 4), L.ring(9)]
+    b = [L.square_torus(4, 4), L.ring(10)]
+    ka, kb = autotune.batch_key(a), autotune.batch_key(b)
+    assert ka == autotune.batch_key(list(a)) and ka != kb
+    assert ka.split(":")[1] == autotune._library_tag()

@@ -155,3 +155,19 @@ def test_batch_errors(api):
         api.BatchPlan([])
     with pytest.raises(api.IsingError, match="member 1"):
         api.BatchPlan([L.ring(5), L.Lattice(3, [0], [0], [1])])
+
+
+def test_autotuner_picks_a_valid_tune_and_caches_it(api, tmp_path, monkeypatch):
+    from paper_1110_2561_amd import autotune
+    monkeypatch.setenv("ISING_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    lats = small_batch()
+    cands = [api.Tune(), api.Tune(inner_bits=10), api.Tune(replicas=4)]
+    tune, timings = autotune.autotune_batch(lats, candidates=cands, reps=1)
+    assert tune in cands and len(timings) == 3 and all(t > 0 for t in timings.values())
+    assert (tmp_path / "tune.json").exists()
+    again, t2 = autotune.autotune_batch(lats, candidates=cands, reps=1)   # from the cache
+    assert again == tune and t2 == timings
+    g = api.batch_enumerate(api.BatchPlan(lats, tune)).cpu()              # the choice is exact too
+    plan = api.BatchPlan(lats)
+    for i, lat in enumerate(lats):
+        np.testing.assert_array_equal(plan.table(g, i).numpy(), _bf(lat))
