@@ -223,11 +223,14 @@ ising_status ising_bond_backward_symmetric(const ising_plan *plan, const double 
  * overlap in time (serialise them on one stream). */
 typedef struct ising_batch_plan ising_batch_plan;
 
-/* n lattices (host array of n descriptors, read during the call only);
- * tune may be NULL.  Each member's chunk width is tune.inner_bits (default
- * 14, at most the member's N) unless tune.prefix_bits is given; tile_bits is
- * an upper bound on each member's tile width; replicas, waves_per_block and
- * max_blocks apply to every member. */
+/* n lattices, 1 <= n <= 65535 (host array of n descriptors, read during the
+ * call only); tune may be NULL.  Each member's chunk width is
+ * tune.inner_bits (default 14, at most the member's N) unless
+ * tune.prefix_bits is given, except that the smallest members, together
+ * about one round of work units over 256 CUs (last in the work list), take
+ * chunks of at most 2^12 configurations so the launch ends on short units;
+ * tile_bits is an upper bound on each member's tile width; replicas,
+ * waves_per_block and max_blocks apply to every member. */
 ising_status ising_batch_plan_create(const ising_lattice *lattices, int32_t n, const ising_tune *tune,
                                      ising_batch_plan **plan);
 ising_status ising_batch_plan_destroy(ising_batch_plan *plan);

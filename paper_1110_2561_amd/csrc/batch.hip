@@ -199,12 +199,15 @@ struct ising_graph {
 constexpr int kTailTaskBits = 10;
 constexpr int kTailBlocks = 256;
 constexpr int kTailInner = 12;
+// Per-member kernels index members by grid y (at most 65535).
+constexpr int kMaxMembers = 65535;
 
 extern "C" ising_status ising_batch_plan_create(const ising_lattice *lats, int32_t n, const ising_tune *tune,
                                                 ising_batch_plan **out) {
   if (!out) return fail(ISING_EINVAL, "plan output pointer is NULL");
   *out = nullptr;
   if (n < 1 || !lats) return fail(ISING_EINVAL, "need at least one lattice");
+  if (n > kMaxMembers) return fail(ISING_EINVAL, "at most " + std::to_string(kMaxMembers) + " lattices per batch");
   ising_tune tn{};
   if (tune) tn = *tune;
   // Members keep their own chunk width: inner_bits (default 14, at most N)

@@ -145,6 +145,8 @@ def test_batch_plan_errors_name_the_member():
         BatchPlan([])
     with pytest.raises(IsingError, match="member 1"):
         BatchPlan([L.ring(5), L.Lattice(3, [0], [0], [1])])
+    with pytest.raises(IsingError, match="65535"):
+        BatchPlan([L.ring(3)] * 65536)
 
 
 def test_wrappers_reject_tables_a_kernel_cannot_read():
