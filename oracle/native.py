@@ -45,6 +45,8 @@ def _load():
             lib.oracle_bond_split.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, ctypes.c_int,
                                               u64p, u64p]
             lib.oracle_bond_split.restype = ctypes.c_int
+            lib.oracle_band_count.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, u64p]
+            lib.oracle_band_count.restype = ctypes.c_int
             _lib = lib
         return _lib
 
@@ -109,6 +111,22 @@ def tm_torus(Jh, Jv, n_threads: int | None = None) -> np.ndarray:
                              g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     if rc != 0:
         raise ValueError(f"oracle_tm_torus failed ({rc})")
+    return g
+
+
+def band_count(n_spins: int, bond_i, bond_j, bond_J) -> np.ndarray:
+    """Exact g by the banded count along the site order (oracle.c), for
+    lattices whose bonds join sites at most 20 apart: uint64 [2S+1][N+1]."""
+    lib = _load()
+    bi, pbi = _i32(bond_i)
+    bj, pbj = _i32(bond_j)
+    bJ, pbJ = _i32(bond_J)
+    S = int(np.abs(bJ.astype(np.int64)).sum())
+    g = np.zeros((2 * S + 1, n_spins + 1), dtype=np.uint64)
+    rc = lib.oracle_band_count(int(n_spins), int(bi.shape[0]), pbi, pbj, pbJ,
+                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    if rc != 0:
+        raise ValueError(f"oracle_band_count failed ({rc})")
     return g
 
 

@@ -27,7 +27,10 @@
  *                        the brute force and to reach the 6x6 / 8x5 sizes);
  *   oracle_bond_split  : g together with, for every bond, the count of the
  *                        configurations of each (E, n_up) whose two spins agree
- *                        (the statistics behind derivatives in the couplings).
+ *                        (the statistics behind derivatives in the couplings);
+ *   oracle_band_count  : a count along the site order for lattices whose bonds
+ *                        join sites at most B apart (a third algorithm, for
+ *                        free-boundary patches too large to enumerate).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -315,4 +318,83 @@ int oracle_bond_split(int n, int nb, const int32_t *bi, const int32_t *bj, const
   for (int t = 0; t < made; ++t) { free(jobs[t].table); free(jobs[t].split); free(jobs[t].agree); }
   free(jobs); free(th);
   return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Banded count: sites in index order, bonds at most B sites apart.         */
+/* ---------------------------------------------------------------------- */
+/* Adding site k with spin s_k adds -J s_i s_k for its bonds to earlier sites
+ * i >= k - B (Eq. (1), each bond once, at its later end), and 1 to n_up if
+ * s_k = +1.  So the counts of the first k + 1 spins need only the spins of the
+ * last B sites: F_k[state][E + S][n_up], state bit d - 1 = spin of site k - d
+ * (d = 1..B; bit set = +1).  Summing F_{N-1} over the states gives g.  Exact
+ * integer arithmetic throughout.  Returns -1 on bad input, -2 if the
+ * bandwidth exceeds 20, -3 if the tables would exceed 2^28 entries, -4 if
+ * out of memory. */
+int oracle_band_count(int n, int nb, const int32_t *bi, const int32_t *bj, const int32_t *bJ, uint64_t *g) {
+  if (n < 1 || n > 64 || nb < 0 || !g) return -1;
+  int64_t S = 0;
+  int B = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (bi[b] < 0 || bi[b] >= n || bj[b] < 0 || bj[b] >= n || bi[b] == bj[b]) return -1;
+    S += bJ[b] < 0 ? -(int64_t)bJ[b] : bJ[b];
+    const int d = bi[b] > bj[b] ? bi[b] - bj[b] : bj[b] - bi[b];
+    if (d > B) B = d;
+  }
+  if (B > 20) return -2;
+  const int64_t ne = 2 * S + 1, nm = n + 1;
+  const size_t cells = (size_t)ne * (size_t)nm;
+  const size_t states = (size_t)1 << B;
+  if ((double)states * (double)cells > (double)((size_t)1 << 28)) return -3;
+  /* bonds grouped by their later end: (distance, coupling) */
+  int *cnt = (int *)calloc((size_t)n, sizeof(int));
+  int *start = (int *)calloc((size_t)n + 1, sizeof(int));
+  int *dist = (int *)malloc(sizeof(int) * (size_t)(nb > 0 ? nb : 1));
+  int64_t *cJ = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb > 0 ? nb : 1));
+  uint64_t *F = (uint64_t *)calloc(states * cells, sizeof(uint64_t));
+  uint64_t *G = (uint64_t *)calloc(states * cells, sizeof(uint64_t));
+  if (!cnt || !start || !dist || !cJ || !F || !G) {
+    free(cnt); free(start); free(dist); free(cJ); free(F); free(G);
+    return -4;
+  }
+  for (int b = 0; b < nb; ++b) ++cnt[bi[b] > bj[b] ? bi[b] : bj[b]];
+  for (int k = 0; k < n; ++k) start[k + 1] = start[k] + cnt[k];
+  memset(cnt, 0, sizeof(int) * (size_t)n);
+  for (int b = 0; b < nb; ++b) {
+    const int hi = bi[b] > bj[b] ? bi[b] : bj[b], lo = bi[b] > bj[b] ? bj[b] : bi[b];
+    const int slot = start[hi] + cnt[hi]++;
+    dist[slot] = hi - lo;
+    cJ[slot] = bJ[b];
+  }
+  const size_t mask = states - 1;
+  F[(size_t)S * (size_t)nm] = 1;           /* no spins yet: state 0, E = 0, n_up = 0 */
+  for (int k = 0; k < n; ++k) {
+    memset(G, 0, sizeof(uint64_t) * states * cells);
+    for (size_t st = 0; st < states; ++st) {
+      const uint64_t *src = F + st * cells;
+      for (int s = 0; s <= 1; ++s) {
+        const int64_t sk = s ? 1 : -1;
+        int64_t de = 0;
+        for (int q = start[k]; q < start[k + 1]; ++q) {
+          const int64_t si = ((st >> (dist[q] - 1)) & 1u) ? 1 : -1;
+          de -= cJ[q] * si * sk;
+        }
+        const size_t ns = B ? (((st << 1) | (size_t)s) & mask) : 0;
+        uint64_t *dst = G + ns * cells;
+        for (int64_t e = 0; e < ne; ++e) {
+          const int64_t e2 = e + de;
+          if (e2 < 0 || e2 >= ne) continue;
+          const uint64_t *a = src + (size_t)e * (size_t)nm;
+          uint64_t *c = dst + (size_t)e2 * (size_t)nm;
+          for (int u = 0; u + s < nm; ++u) c[u + s] += a[u];
+        }
+      }
+    }
+    uint64_t *t = F; F = G; G = t;
+  }
+  memset(g, 0, sizeof(uint64_t) * cells);
+  for (size_t st = 0; st < states; ++st)
+    for (size_t c = 0; c < cells; ++c) g[c] += F[st * cells + c];
+  free(cnt); free(start); free(dist); free(cJ); free(F); free(G);
+  return 0;
 }

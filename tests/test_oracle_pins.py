@@ -232,3 +232,49 @@ def test_planted_energy_offset_breaks_kaufman_pin():
     ref = float(closed_forms.kaufman_logz(4, 4, 2.0))
     assert abs(thermo.log_z(g, -32, 16, [2.0], [0.0])[0, 0] - ref) < 1e-13
     assert abs(thermo.log_z(g, -31, 16, [2.0], [0.0])[0, 0] - ref) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# banded count along the site order (free-boundary patches)
+# ---------------------------------------------------------------------------
+
+def _band(lat):
+    return native.band_count(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J)
+
+
+def test_band_count_matches_table1():
+    lat = L.square_torus(4, 4)                     # bandwidth 12 with the wrap bonds
+    assert nonzero_bins(_band(lat), -32, 16) == load_table1()
+
+
+@pytest.mark.parametrize("lat", [
+    L.triangular_free(19, 5, L.choice_couplings(L.triangular_free(19, 5).n_bonds, 4)),
+    L.triangular_free(22, 6, L.choice_couplings(L.triangular_free(22, 6).n_bonds, 9)),
+    L.triangular_free(17, 4, L.pm_couplings(L.triangular_free(17, 4).n_bonds, 5)),
+    L.ring(11, L.pm_couplings(11, 2)),
+    L.Lattice(6, [0, 1, 1, 2, 4, 0, 5], [1, 2, 2, 3, 5, 5, 3], [1, -2, 3, 1, -1, 2, 2]),   # repeated pair
+    L.Lattice(7, [], [], []),
+    L.Lattice(1, [], [], []),
+], ids=lambda l: f"{l.kind}{l.n_spins}")
+def test_band_count_matches_bruteforce(lat):
+    np.testing.assert_array_equal(_band(lat), _g(lat))
+
+
+def test_band_count_matches_transfer_matrix_on_a_torus():
+    lat = L.square_torus(3, 5, L.choice_couplings(30, 13))          # bandwidth 12
+    np.testing.assert_array_equal(_band(lat), _tm(lat))
+
+
+def test_band_count_refuses_wide_or_bad_lattices():
+    with pytest.raises(ValueError):
+        native.band_count(30, [0], [29], [1])                        # bandwidth 29 > 20
+    with pytest.raises(ValueError):
+        native.band_count(4, [0], [0], [1])                          # self-bond
+
+
+def test_planted_sign_flip_breaks_band_count():
+    # one bond's coupling negated (same table shape) must change the count
+    lat = L.triangular_free(16, 4, L.choice_couplings(L.triangular_free(16, 4).n_bonds, 3))
+    J = lat.bond_J.copy()
+    J[7] = -J[7]
+    assert not np.array_equal(native.band_count(16, lat.bond_i, lat.bond_j, J), _g(lat))
