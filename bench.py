@@ -320,7 +320,7 @@ def main() -> int:
         return copy_calibration(args.copy_calibration)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(sharding would split the chunk range per GPU and sum the uint64 tables); "
               "run with --gpus 1", file=sys.stderr)
         return 2

@@ -52,7 +52,7 @@ typedef enum ising_status {
   ISING_ERANGE = -4,            /* couplings too large: S > 2^20, or histogram exceeds LDS */
   ISING_EHIP = -5,              /* a HIP runtime call failed (message has the HIP error) */
   ISING_ENOMEM = -6,            /* host or device allocation failed */
-  ISING_EUNSUPPORTED = -7       /* valid input outside what this build handles
+  ISING_EUNSUPPORTED = -7       /* valid input outside what the library handles
                                    (e.g. more than 8 distinct coupling values) */
 } ising_status;
 
