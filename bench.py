@@ -50,6 +50,21 @@ COUNTERS = {
 }
 
 
+def sources_sha256() -> str:
+    """SHA-256 over the library's C/HIP sources and header (provenance of the
+    measured build; the line may be produced where no git history exists)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(_ROOT, "paper_1110_2561_amd", "csrc", "*"))) + \
+        [os.path.join(_ROOT, "include", "ising.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def counters_valid(workload: str) -> bool:
     import hashlib
     if workload != COUNTERS["workload"]:
@@ -428,6 +443,8 @@ def main() -> int:
             },
         },
     }
+    line["build"] = {"sources_sha256": sources_sha256(), "arch": torch.cuda.get_device_properties(0).gcnArchName,
+                     "cus": torch.cuda.get_device_properties(0).multi_processor_count}
     if not args.no_extras:
         line["z2_halving"] = bench_symmetric(plan, g, configs, achieved, reps=5)
         line["batched"] = bench_batched(achieved, reps=5)
