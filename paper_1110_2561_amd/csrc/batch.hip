@@ -11,7 +11,10 @@
 // units from a device counter.  A block keeps one member's histogram in LDS
 // and flushes it to that member's table whenever it moves to another member
 // (or before its counters could overflow), so consecutive units of a large
-// member cost no flush.
+// member cost no flush.  The smallest members, last in the list, take short
+// chunks so that the launch ends on short units.  A second, halved work list
+// covers only the chunks with each member's top spin up; k_batch_mirror then
+// completes every table from the spin-flip symmetry.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
