@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from conftest import load_table1, nonzero_bins
-from oracle import native
+from oracle import closed_forms, native
 from paper_1110_2561_amd import lattice as L
 
 pytestmark = pytest.mark.gpu
@@ -304,3 +304,26 @@ def test_seeded_random_sweep(api, k):
         for sym in (False, True):
             dJ = api.bond_backward(plan, torch.from_numpy(W).cuda(), symmetric=sym).cpu().numpy()
             np.testing.assert_allclose(dJ, refJ, rtol=0, atol=1e-13 * scale)
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_property_sweep_21_to_30_spins(api, k):
+    """Seeded random multigraphs of 21-30 spins (brute force is too slow here):
+    sum g = 2^N, binomial marginals, g(E, M) = g(E, -M), and the halved and
+    range-split tables equal to the full one."""
+    rng = L.SplitMix64(777 + k)
+    n = 21 + rng.next() % 10
+    lat = L.random_bond_lattice(n, n + rng.next() % (2 * n), rng.next() & 0xFFFFFFFF,
+                                values=[(-1, 1), (-2, -1, 1, 2), (1,), (-3, 2)][k % 4])
+    plan = api.Plan(lat)
+    print(f"case {k}: N={n} bonds={lat.n_bonds} chunks={plan.n_chunks}", flush=True)
+    g = api.enumerate_g(plan).cpu().numpy()
+    assert int(g.sum(dtype=np.uint64)) == 1 << n
+    np.testing.assert_array_equal(g.sum(axis=0).astype(object), closed_forms.binomial_marginal(n))
+    np.testing.assert_array_equal(g, g[:, ::-1])
+    np.testing.assert_array_equal(api.enumerate_symmetric(plan).cpu().numpy(), g)
+    parts = torch.zeros((plan.n_e, plan.n_m), dtype=torch.uint64, device="cuda")
+    cuts = sorted({0, plan.n_chunks, *[int(rng.next() % (plan.n_chunks + 1)) for _ in range(3)]})
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        api.enumerate_range(plan, a, b - a, parts)
+    np.testing.assert_array_equal(parts.cpu().numpy(), g)
