@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from .lattice import Lattice
 
-__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_symmetric", "enumerate_range", "log_z", "moments", "IsingError",
+__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_symmetric", "enumerate_range", "log_z", "moments", "per_spin",
+           "IsingError",
            "logz_derivatives", "bin_weights", "bond_backward",
            "BatchPlan", "batch_enumerate", "batch_moments", "BatchGraph"]
 
@@ -170,6 +171,16 @@ def moments(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dic
                                   outs["mean_M"].data_ptr(), outs["heat_capacity"].data_ptr(),
                                   outs["susceptibility"].data_ptr(), _stream_handle(stream)))
     return outs
+
+
+def per_spin(m: dict, n_spins: int, T) -> dict:
+    """Intensive forms of the totals moments() returns: <E>/N, <M>/N, C/N,
+    chi/N, log Z / N, and the free energy per spin f = -T log Z / N (the
+    library's C and chi are totals over the N spins)."""
+    Tt = _grid(T, m["log_z"].device).reshape(-1, 1)
+    out = {k: m[k] / n_spins for k in ("log_z", "mean_E", "mean_M", "heat_capacity", "susceptibility")}
+    out["free_energy"] = -Tt * m["log_z"] / n_spins
+    return out
 
 
 def logz_derivatives(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dict:
