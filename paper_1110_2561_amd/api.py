@@ -81,10 +81,13 @@ class Plan:
     @property
     def bond_workspace_bytes(self) -> int:
         """Device workspace of bond_backward (ising_bond_workspace); raises
-        IsingError when the per-bond backward does not support this lattice."""
-        n = ctypes.c_size_t()
-        _lib.check(_lib.ising_bond_workspace(self._h, ctypes.byref(n)))
-        return n.value
+        IsingError when the per-bond backward does not support this lattice.
+        A plan is immutable, so the size is asked for once."""
+        if getattr(self, "_bw_bytes", None) is None:
+            n = ctypes.c_size_t()
+            _lib.check(_lib.ising_bond_workspace(self._h, ctypes.byref(n)))
+            self._bw_bytes = n.value
+        return self._bw_bytes
 
     def close(self):
         if getattr(self, "_h", None):
