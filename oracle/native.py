@@ -19,10 +19,10 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (plain C, gcc -O2)."""
+    """Compile oracle.c into liboracle.so (plain C, gcc -O2 with the x86-64 popcount instruction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC]
+        cmd = ["gcc", "-O2", "-mpopcnt", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -47,6 +47,9 @@ def _load():
             lib.oracle_bond_split.restype = ctypes.c_int
             lib.oracle_band_count.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, u64p]
             lib.oracle_band_count.restype = ctypes.c_int
+            lib.oracle_row_words.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.c_int, u64p]
+            lib.oracle_row_words.restype = ctypes.c_int
             _lib = lib
         return _lib
 
@@ -111,6 +114,22 @@ def tm_torus(Jh, Jv, n_threads: int | None = None) -> np.ndarray:
                              g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     if rc != 0:
         raise ValueError(f"oracle_tm_torus failed ({rc})")
+    return g
+
+
+def row_words(Lx: int, Ly: int, first: int = 0, count: int | None = None,
+              n_threads: int | None = None) -> np.ndarray:
+    """g of the Lx x Ly square torus with J = 1 by the paper's bit-word scheme
+    (Section 3), over configurations [first, first + count) (default all):
+    uint64 [4N+1][N+1], row E + 2N, column n_up."""
+    lib = _load()
+    N = Lx * Ly
+    count = (1 << N) - first if count is None else count
+    g = np.zeros((4 * N + 1, N + 1), dtype=np.uint64)
+    rc = lib.oracle_row_words(int(Lx), int(Ly), int(first), int(count), int(n_threads or default_threads()),
+                              g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    if rc != 0:
+        raise ValueError(f"oracle_row_words failed ({rc})")
     return g
 
 

@@ -30,7 +30,11 @@
  *                        (the statistics behind derivatives in the couplings);
  *   oracle_band_count  : a count along the site order for lattices whose bonds
  *                        join sites at most B apart (a third algorithm, for
- *                        free-boundary patches too large to enumerate).
+ *                        free-boundary patches too large to enumerate);
+ *   oracle_row_words   : the paper's own scheme (Section 3) for the square
+ *                        torus with J = 1: the lattice as one bit word per
+ *                        row, satisfied bonds counted with XOR, NOT, a mask
+ *                        and popcount, E = 2 (N - En), M from popcounts.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -397,4 +401,76 @@ int oracle_band_count(int n, int nb, const int32_t *bi, const int32_t *bj, const
     for (size_t c = 0; c < cells; ++c) g[c] += F[st * cells + c];
   free(cnt); free(start); free(dist); free(cJ); free(F); free(G);
   return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The paper's scheme for the J = 1 square torus (Section 3a-c).            */
+/* ---------------------------------------------------------------------- */
+/* A configuration is Ly words of Lx bits, word r = row r (site (x, r) is bit
+ * x, index r * Lx + x, so the word values are the configuration index split
+ * into Lx-bit pieces).  Satisfied bonds En: within a row, XOR of the word
+ * with itself rotated by one bit, NOT, keep the Lx significant bits,
+ * popcount (Section 3b's row pass, on the row's periodic ring); between rows
+ * r and r + 1 (mod Ly), XOR, NOT, mask, popcount (Section 3c).  With 2N
+ * bonds of coupling 1, E = (2N - En) - En = 2 (N - En) (Section 3c), and the
+ * up count is the sum of the words' popcounts (Section 3a). */
+
+typedef struct {
+  int Lx, Ly;
+  uint64_t lo, hi;
+  uint64_t *table;   /* private [4N + 1][N + 1] */
+} words_job;
+
+static void *words_worker(void *arg) {
+  words_job *jb = (words_job *)arg;
+  const int Lx = jb->Lx, Ly = jb->Ly, N = Lx * Ly, nm = N + 1;
+  const uint64_t mask = (Lx == 64) ? ~0ull : ((1ull << Lx) - 1);
+  uint64_t a[64];
+  for (uint64_t c = jb->lo; c < jb->hi; ++c) {
+    int En = 0, up = 0;
+    for (int r = 0; r < Ly; ++r) a[r] = (c >> (r * Lx)) & mask;
+    for (int r = 0; r < Ly; ++r) {
+      const uint64_t rot = ((a[r] >> 1) | (a[r] << (Lx - 1))) & mask;     /* bit x <- bit x + 1 (mod Lx) */
+      En += __builtin_popcountll(~(a[r] ^ rot) & mask);
+      En += __builtin_popcountll(~(a[r] ^ a[(r + 1) % Ly]) & mask);
+      up += __builtin_popcountll(a[r]);
+    }
+    const int E = 2 * (N - En);
+    jb->table[(size_t)(E + 2 * N) * (size_t)nm + (size_t)up] += 1;
+  }
+  return NULL;
+}
+
+/* Counts of configurations [first, first + count) of the Lx x Ly torus with
+ * every coupling 1 (S = 2N), into g [4N + 1][N + 1] (overwritten).  Needs
+ * Lx, Ly >= 3 (a side of 2 doubles bonds; the row pass above would count a
+ * doubled bond once) and N <= 40. */
+int oracle_row_words(int Lx, int Ly, uint64_t first, uint64_t count, int n_threads, uint64_t *g) {
+  if (Lx < 3 || Ly < 3 || Lx * Ly > 40 || n_threads < 1 || !g) return -1;
+  const int N = Lx * Ly;
+  const size_t cells = (size_t)(4 * N + 1) * (size_t)(N + 1);
+  if (first > (1ull << N) || count > (1ull << N) - first) return -1;
+  const uint64_t total = count;
+  if ((uint64_t)n_threads > total) n_threads = total ? (int)total : 1;
+  words_job *jobs = (words_job *)calloc((size_t)n_threads, sizeof(words_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+  if (!jobs || !th) { free(jobs); free(th); return -4; }
+  int rc = 0, made = 0;
+  for (int t = 0; t < n_threads; ++t) {
+    jobs[t] = (words_job){Lx, Ly, first + total / (uint64_t)n_threads * (uint64_t)t,
+                          first + (t == n_threads - 1 ? total : total / (uint64_t)n_threads * (uint64_t)(t + 1)),
+                          (uint64_t *)calloc(cells, sizeof(uint64_t))};
+    if (!jobs[t].table) { rc = -4; break; }
+    made = t + 1;
+  }
+  if (rc == 0) {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, words_worker, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    memset(g, 0, cells * sizeof(uint64_t));
+    for (int t = 0; t < n_threads; ++t)
+      for (size_t k = 0; k < cells; ++k) g[k] += jobs[t].table[k];
+  }
+  for (int t = 0; t < made; ++t) free(jobs[t].table);
+  free(jobs); free(th);
+  return rc;
 }

@@ -278,3 +278,33 @@ def test_planted_sign_flip_breaks_band_count():
     J = lat.bond_J.copy()
     J[7] = -J[7]
     assert not np.array_equal(native.band_count(16, lat.bond_i, lat.bond_j, J), _g(lat))
+
+
+# ---------------------------------------------------------------------------
+# the paper's own scheme: row bit words, XOR / NOT / mask / popcount (Section 3)
+# ---------------------------------------------------------------------------
+
+def test_row_words_matches_table1():
+    assert nonzero_bins(native.row_words(4, 4), -32, 16) == load_table1()
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (3, 5), (4, 5), (5, 4), (5, 5), (4, 6)])
+def test_row_words_matches_transfer_matrix(shape):
+    lat = L.square_torus(*shape)
+    np.testing.assert_array_equal(native.row_words(*shape), _tm(lat))
+
+
+def test_row_words_ranges_match_bruteforce_and_add_up():
+    lat = L.square_torus(4, 5)
+    ref = _g(lat)
+    first, count = 12345, 1 << 17
+    np.testing.assert_array_equal(native.row_words(4, 5, first, count),
+                                  native.count_range(20, lat.bond_i, lat.bond_j, lat.bond_J, first, count))
+    parts = native.row_words(4, 5, 0, 777) + native.row_words(4, 5, 777, (1 << 20) - 777)
+    np.testing.assert_array_equal(parts, ref)
+
+
+def test_row_words_refuses_doubled_bonds_and_large_tori():
+    for shape in [(2, 5), (5, 2), (7, 6)]:
+        with pytest.raises(ValueError):
+            native.row_words(*shape)
