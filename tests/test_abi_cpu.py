@@ -189,3 +189,12 @@ def test_per_spin_forms():
     p = api.per_spin(m, 4, T)
     assert torch.equal(p["heat_capacity"], m["heat_capacity"] / 4)
     assert torch.allclose(p["free_energy"], -torch.tensor([[0.5], [2.0]], dtype=torch.float64) * m["log_z"] / 4)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the library has no multi-GPU path; bench.py says so and exits non-zero
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
