@@ -47,8 +47,8 @@ def _load():
             lib.oracle_bond_split.restype = ctypes.c_int
             lib.oracle_band_count.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, i32p, u64p]
             lib.oracle_band_count.restype = ctypes.c_int
-            lib.oracle_row_words.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
-                                             ctypes.c_int, u64p]
+            lib.oracle_row_words.argtypes = [ctypes.c_int, ctypes.c_int, u64p, u64p, ctypes.c_uint64,
+                                             ctypes.c_uint64, ctypes.c_int, u64p]
             lib.oracle_row_words.restype = ctypes.c_int
             _lib = lib
         return _lib
@@ -118,16 +118,31 @@ def tm_torus(Jh, Jv, n_threads: int | None = None) -> np.ndarray:
 
 
 def row_words(Lx: int, Ly: int, first: int = 0, count: int | None = None,
-              n_threads: int | None = None) -> np.ndarray:
-    """g of the Lx x Ly square torus with J = 1 by the paper's bit-word scheme
-    (Section 3), over configurations [first, first + count) (default all):
-    uint64 [4N+1][N+1], row E + 2N, column n_up."""
+              n_threads: int | None = None, Jh=None, Jv=None) -> np.ndarray:
+    """g of the Lx x Ly square torus with couplings +-1 by the paper's bit-word
+    scheme (Section 3), over configurations [first, first + count) (default
+    all): uint64 [4N+1][N+1], row E + 2N, column n_up.  Jh, Jv are the
+    [Ly][Lx] coupling grids of lattice.torus_coupling_grids (entries +-1;
+    default all 1): Jh[y][x] couples (x, y)-(x+1, y), Jv[y][x] couples
+    (x, y)-(x, y+1).  A J = -1 bond is satisfied when its spins differ, which
+    the scheme handles with one more XOR against a per-row sign mask."""
     lib = _load()
     N = Lx * Ly
     count = (1 << N) - first if count is None else count
+    masks = []
+    for grid in (Jh, Jv):
+        m = np.zeros(max(Ly, 1), dtype=np.uint64)
+        if grid is not None:
+            grid = np.asarray(grid, dtype=np.int64)
+            if grid.shape != (Ly, Lx) or not np.isin(grid, (-1, 1)).all():
+                raise ValueError("coupling grids must be [Ly][Lx] with entries +-1")
+            for y in range(Ly):
+                m[y] = sum(1 << x for x in range(Lx) if grid[y, x] < 0)
+        masks.append(m)
     g = np.zeros((4 * N + 1, N + 1), dtype=np.uint64)
-    rc = lib.oracle_row_words(int(Lx), int(Ly), int(first), int(count), int(n_threads or default_threads()),
-                              g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    pu = ctypes.POINTER(ctypes.c_uint64)
+    rc = lib.oracle_row_words(int(Lx), int(Ly), masks[0].ctypes.data_as(pu), masks[1].ctypes.data_as(pu),
+                              int(first), int(count), int(n_threads or default_threads()), g.ctypes.data_as(pu))
     if rc != 0:
         raise ValueError(f"oracle_row_words failed ({rc})")
     return g

@@ -32,9 +32,11 @@
  *                        join sites at most B apart (a third algorithm, for
  *                        free-boundary patches too large to enumerate);
  *   oracle_row_words   : the paper's own scheme (Section 3) for the square
- *                        torus with J = 1: the lattice as one bit word per
- *                        row, satisfied bonds counted with XOR, NOT, a mask
- *                        and popcount, E = 2 (N - En), M from popcounts.
+ *                        torus with couplings +-1: the lattice as one bit
+ *                        word per row, satisfied bonds counted with XOR, NOT,
+ *                        a mask and popcount (and, for J = -1 bonds, one more
+ *                        XOR with the row's sign mask), E = 2 (N - En), M from
+ *                        popcounts.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -404,20 +406,26 @@ int oracle_band_count(int n, int nb, const int32_t *bi, const int32_t *bj, const
 }
 
 /* ---------------------------------------------------------------------- */
-/* The paper's scheme for the J = 1 square torus (Section 3a-c).            */
+/* The paper's scheme for the square torus with couplings +-1 (Section 3a-c). */
 /* ---------------------------------------------------------------------- */
 /* A configuration is Ly words of Lx bits, word r = row r (site (x, r) is bit
  * x, index r * Lx + x, so the word values are the configuration index split
- * into Lx-bit pieces).  Satisfied bonds En: within a row, XOR of the word
- * with itself rotated by one bit, NOT, keep the Lx significant bits,
- * popcount (Section 3b's row pass, on the row's periodic ring); between rows
- * r and r + 1 (mod Ly), XOR, NOT, mask, popcount (Section 3c).  With 2N
- * bonds of coupling 1, E = (2N - En) - En = 2 (N - En) (Section 3c), and the
- * up count is the sum of the words' popcounts (Section 3a). */
+ * into Lx-bit pieces).  A bond is satisfied when J s_i s_j = +1: for J = 1
+ * when its spins agree, for J = -1 when they differ (Eq. (1) allows
+ * sign-changing couplings, Section 2).  Satisfied bonds En: within a row,
+ * XOR of the word with itself rotated by one bit, NOT, then XOR with the
+ * row's mask of J = -1 bonds, keep the Lx significant bits, popcount
+ * (Section 3b's row pass, on the row's periodic ring); between rows r and
+ * r + 1 (mod Ly) the same with the two words and the vertical sign mask
+ * (Section 3c).  With 2N bonds of |J| = 1, E = (2N - En) - En = 2 (N - En)
+ * (Section 3c), and the up count is the sum of the words' popcounts
+ * (Section 3a).  With all couplings 1 the sign masks are zero and this is
+ * the paper's J = 1 scheme unchanged. */
 
 typedef struct {
   int Lx, Ly;
   uint64_t lo, hi;
+  const uint64_t *neg_h, *neg_v;   /* per row: bit x set when that bond has J = -1 */
   uint64_t *table;   /* private [4N + 1][N + 1] */
 } words_job;
 
@@ -431,8 +439,8 @@ static void *words_worker(void *arg) {
     for (int r = 0; r < Ly; ++r) a[r] = (c >> (r * Lx)) & mask;
     for (int r = 0; r < Ly; ++r) {
       const uint64_t rot = ((a[r] >> 1) | (a[r] << (Lx - 1))) & mask;     /* bit x <- bit x + 1 (mod Lx) */
-      En += __builtin_popcountll(~(a[r] ^ rot) & mask);
-      En += __builtin_popcountll(~(a[r] ^ a[(r + 1) % Ly]) & mask);
+      En += __builtin_popcountll((~(a[r] ^ rot) ^ jb->neg_h[r]) & mask);
+      En += __builtin_popcountll((~(a[r] ^ a[(r + 1) % Ly]) ^ jb->neg_v[r]) & mask);
       up += __builtin_popcountll(a[r]);
     }
     const int E = 2 * (N - En);
@@ -442,14 +450,22 @@ static void *words_worker(void *arg) {
 }
 
 /* Counts of configurations [first, first + count) of the Lx x Ly torus with
- * every coupling 1 (S = 2N), into g [4N + 1][N + 1] (overwritten).  Needs
+ * couplings +-1, into g [4N + 1][N + 1] (overwritten).  neg_h[r] bit x is
+ * set when the bond (x, r)-(x+1 mod Lx, r) has J = -1, neg_v[r] bit x when
+ * (x, r)-(x, r+1 mod Ly) has; either may be NULL (all J = 1).  Needs
  * Lx, Ly >= 3 (a side of 2 doubles bonds; the row pass above would count a
  * doubled bond once) and N <= 40. */
-int oracle_row_words(int Lx, int Ly, uint64_t first, uint64_t count, int n_threads, uint64_t *g) {
+int oracle_row_words(int Lx, int Ly, const uint64_t *neg_h, const uint64_t *neg_v, uint64_t first,
+                     uint64_t count, int n_threads, uint64_t *g) {
   if (Lx < 3 || Ly < 3 || Lx * Ly > 40 || n_threads < 1 || !g) return -1;
   const int N = Lx * Ly;
   const size_t cells = (size_t)(4 * N + 1) * (size_t)(N + 1);
   if (first > (1ull << N) || count > (1ull << N) - first) return -1;
+  uint64_t nh[64] = {0}, nv[64] = {0};
+  for (int r = 0; r < Ly; ++r) {
+    nh[r] = neg_h ? neg_h[r] : 0;
+    nv[r] = neg_v ? neg_v[r] : 0;
+  }
   const uint64_t total = count;
   if ((uint64_t)n_threads > total) n_threads = total ? (int)total : 1;
   words_job *jobs = (words_job *)calloc((size_t)n_threads, sizeof(words_job));
@@ -459,7 +475,7 @@ int oracle_row_words(int Lx, int Ly, uint64_t first, uint64_t count, int n_threa
   for (int t = 0; t < n_threads; ++t) {
     jobs[t] = (words_job){Lx, Ly, first + total / (uint64_t)n_threads * (uint64_t)t,
                           first + (t == n_threads - 1 ? total : total / (uint64_t)n_threads * (uint64_t)(t + 1)),
-                          (uint64_t *)calloc(cells, sizeof(uint64_t))};
+                          nh, nv, (uint64_t *)calloc(cells, sizeof(uint64_t))};
     if (!jobs[t].table) { rc = -4; break; }
     made = t + 1;
   }

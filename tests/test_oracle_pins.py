@@ -308,3 +308,41 @@ def test_row_words_refuses_doubled_bonds_and_large_tori():
     for shape in [(2, 5), (5, 2), (7, 6)]:
         with pytest.raises(ValueError):
             native.row_words(*shape)
+
+
+@pytest.mark.parametrize("shape,seed", [((3, 3), 1), ((3, 5), 2), ((5, 3), 3), ((4, 5), 4), ((5, 4), 5),
+                                        ((4, 6), 6), ((6, 4), 7)])
+def test_row_words_pm_matches_transfer_matrix(shape, seed):
+    # +-J couplings (Section 2 allows sign-changing J): a J = -1 bond is
+    # satisfied when its spins differ; the transfer matrix is an independent count
+    lat = L.square_torus(*shape, L.pm_couplings(2 * shape[0] * shape[1], seed))
+    Jh, Jv = L.torus_coupling_grids(lat)
+    assert (Jh < 0).any() and (Jv < 0).any()
+    np.testing.assert_array_equal(native.row_words(*shape, Jh=Jh, Jv=Jv), _tm(lat))
+
+
+def test_row_words_pm_ranges_match_bruteforce_and_add_up():
+    lat = L.square_torus(5, 4, L.pm_couplings(40, 11))
+    Jh, Jv = L.torus_coupling_grids(lat)
+    first, count = 54321, 1 << 17
+    np.testing.assert_array_equal(native.row_words(5, 4, first, count, Jh=Jh, Jv=Jv),
+                                  native.count_range(20, lat.bond_i, lat.bond_j, lat.bond_J, first, count))
+    parts = native.row_words(5, 4, 0, 999, Jh=Jh, Jv=Jv) + native.row_words(5, 4, 999, (1 << 20) - 999,
+                                                                           Jh=Jh, Jv=Jv)
+    np.testing.assert_array_equal(parts, _g(lat))
+
+
+def test_row_words_pm_is_sensitive_to_each_sign():
+    # a planted mistake in the couplings (one sign flipped, or the two grids
+    # exchanged) must change the table
+    lat = L.square_torus(4, 5, L.pm_couplings(40, 12))
+    Jh, Jv = L.torus_coupling_grids(lat)
+    ref = native.row_words(4, 5, Jh=Jh, Jv=Jv)
+    for grid in ("h", "v"):
+        for y, x in [(0, 0), (2, 3), (4, 1)]:
+            a, b = Jh.copy(), Jv.copy()
+            (a if grid == "h" else b)[y, x] *= -1
+            assert not np.array_equal(native.row_words(4, 5, Jh=a, Jv=b), ref), (grid, y, x)
+    assert not np.array_equal(native.row_words(4, 5, Jh=Jv, Jv=Jh), ref)
+    with pytest.raises(ValueError):
+        native.row_words(4, 5, Jh=2 * Jh, Jv=Jv)          # only +-1 couplings
