@@ -33,3 +33,30 @@ def nonzero_bins(g, e_min, n_spins):
     import numpy as np
     e_idx, n_up = np.nonzero(g)
     return {(int(e) + e_min, 2 * int(n) - n_spins): int(g[e, n]) for e, n in zip(e_idx, n_up)}
+
+
+def load_cube_goldens():
+    """{member index: dense uint64 table} of the 3x3x3 cubes of the batch256
+    workload, as the oracle's brute force counted them
+    (tests/golden/make_batch256_cubes.py).  Each entry is checked to belong to
+    the workload's lattice by its coupling seed and a SHA-256 of its bonds."""
+    import hashlib
+
+    import numpy as np
+
+    from paper_1110_2561_amd import lattice as L
+    z = np.load(os.path.join(ROOT, "tests", "golden", "batch256_cubes.npz"))
+    lats = L.workload("batch256")["lattices"]
+    out = {}
+    for c, i in enumerate(z["member"].tolist()):
+        lat = lats[i]
+        h = hashlib.sha256()
+        for a in (lat.bond_i, lat.bond_j, lat.bond_J):
+            h.update(np.ascontiguousarray(a, dtype=np.int32).tobytes())
+        assert lat.kind == "cubic_torus" and int(z["seed"][c]) == lat.seed, f"member {i}"
+        assert z["bonds_sha"][c].decode() == h.hexdigest(), f"member {i}: lattice differs from the golden's"
+        g = np.zeros((int(z["n_e"][c]), lat.n_spins + 1), dtype=np.uint64)
+        a, b = int(z["offsets"][c]), int(z["offsets"][c + 1])
+        g[z["e_idx"][a:b].astype(np.int64), z["n_up"][a:b].astype(np.int64)] = z["count"][a:b]
+        out[i] = g
+    return out
