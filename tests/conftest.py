@@ -60,3 +60,29 @@ def load_cube_goldens():
         g[z["e_idx"][a:b].astype(np.int64), z["n_up"][a:b].astype(np.int64)] = z["count"][a:b]
         out[i] = g
     return out
+
+
+def moment_scales(g, S, N, T, h):
+    """The oracle's moments of a table on a (T, h) grid, and for each
+    derivative of log Z the magnitude of the terms its formula sums or
+    subtracts (a forward error bound is a small multiple of eps times it):
+      d_T  = <H>/T^2               |H| <= S + |h| N
+      d_h  = <M>/T                 |M| <= N
+      d_TT = Var(H)/T^4 - 2<H>/T^3
+      d_Th = (Cov(H, M)/T - <M>)/T^2,  |Cov| <= sqrt(Var(H) Var(M))
+      d_hh = Var(M)/T^2
+    Keys: mE, mM, mH, C, chi (oracle values) and d_T .. d_hh (scales)."""
+    import numpy as np
+
+    from oracle import thermo
+    T = np.atleast_1d(np.asarray(T, dtype=np.float64))
+    h = np.atleast_1d(np.asarray(h, dtype=np.float64))
+    mE, mM, C, chi = thermo.moments(g, -S, N, T, h)
+    Tc, hr = T[:, None], h[None, :]
+    varH, varM = C * Tc * Tc, chi * Tc
+    hmax = S + np.abs(hr) * N + 0 * Tc
+    return {"mE": mE, "mM": mM, "C": C, "chi": chi, "mH": mE - hr * mM, "hmax": hmax,
+            "d_T": hmax / Tc ** 2, "d_h": N / Tc + 0 * hr,
+            "d_TT": varH / Tc ** 4 + 2 * hmax / Tc ** 3,
+            "d_Th": (np.sqrt(varH * varM) / Tc + N) / Tc ** 2,
+            "d_hh": varM / Tc ** 2}

@@ -9,10 +9,17 @@ import numpy as np
 import pytest
 import torch
 
+from conftest import moment_scales
 from oracle import closed_forms, grad, native, thermo
 from paper_1110_2561_amd import lattice as L
 
 pytestmark = pytest.mark.gpu
+
+# Forward error bounds: FP64 evaluations from g within 1e-12 of the magnitude
+# of the terms each formula combines (moment_scales); sums over all 2^N
+# configurations within 1e-13 of sum |W| g.
+TOL = 1e-12
+TOL_SUM = 1e-13
 
 
 @pytest.fixture(scope="module")
@@ -71,9 +78,10 @@ def test_logz_derivatives_match_oracle(api, name):
     out = api.logz_derivatives(_dev_table(g), -S, N, T_GRID, H_GRID)
     ref = grad.log_z_derivatives(g, -S, N, T_GRID, H_GRID)
     np.testing.assert_allclose(out["log_z"].cpu().numpy(), thermo.log_z(g, -S, N, T_GRID, H_GRID), rtol=1e-13)
+    sc = moment_scales(g, S, N, T_GRID, H_GRID)
     for k, v in ref.items():
-        scale = np.abs(v).max() + 1e-300
-        np.testing.assert_allclose(out[k].cpu().numpy(), v, rtol=1e-11, atol=1e-12 * scale, err_msg=k)
+        err = np.abs(out[k].cpu().numpy() - v)
+        assert (err <= TOL * sc[k]).all(), (k, float((err / sc[k]).max()))
 
 
 @pytest.mark.parametrize("name", ["torus4x4", "cubic3_pm", "ring9"])
@@ -258,10 +266,13 @@ def test_autograd_first_derivatives_match_oracle(ag):
     G = np.random.default_rng(3).standard_normal(lz.shape)
     gT, gh, gJ = torch.autograd.grad((lz * torch.from_numpy(G).cuda()).sum(), (T, h, J))
     d = grad.log_z_derivatives(g, -S, N, T_GRID, H_GRID)
-    np.testing.assert_allclose(gT.cpu().numpy(), (G * d["d_T"]).sum(1), rtol=1e-11)
-    np.testing.assert_allclose(gh.cpu().numpy(), (G * d["d_h"]).sum(0), rtol=1e-11, atol=1e-12)
+    sc = moment_scales(g, S, N, T_GRID, H_GRID)
+    assert (np.abs(gT.cpu().numpy() - (G * d["d_T"]).sum(1)) <= TOL * (np.abs(G) * sc["d_T"]).sum(1)).all()
+    assert (np.abs(gh.cpu().numpy() - (G * d["d_h"]).sum(0)) <= TOL * (np.abs(G) * sc["d_h"]).sum(0)).all()
     refJ = (G[None] * grad.bond_grad(g, gp, -S, N, T_GRID, H_GRID)).sum(axis=(1, 2))
-    np.testing.assert_allclose(gJ.cpu().numpy(), refJ, rtol=1e-10, atol=1e-12 * np.abs(refJ).max())
+    Wref = grad.bin_weights(g, -S, N, T_GRID, H_GRID, G)
+    bound = TOL_SUM * (np.abs(Wref) * g.astype(np.float64)).sum()
+    assert (np.abs(gJ.cpu().numpy() - refJ) <= bound).all()
 
 
 def test_autograd_matches_central_finite_differences(ag):
@@ -298,18 +309,21 @@ def test_double_backward_gives_heat_capacity_and_susceptibility(api, ag):
         dT, dh = torch.autograd.grad(lz.sum(), (T, h), create_graph=True)
         H = T * T * dT                         # <E - hM> per temperature
         C = torch.autograd.grad(H.sum(), T, retain_graph=True)[0]
-        mE, mM, Cref, chiref = thermo.moments(g, -S, N, T_GRID, [h0])
-        np.testing.assert_allclose(H.detach().cpu().numpy(), (mE - h0 * mM)[:, 0], rtol=1e-11, atol=1e-12)
-        np.testing.assert_allclose(C.cpu().numpy(), Cref[:, 0], rtol=1e-10)
+        sc = moment_scales(g, S, N, T_GRID, [h0])
+        Cref, chiref, hmax = sc["C"], sc["chi"], sc["hmax"][:, 0]
+        assert (np.abs(H.detach().cpu().numpy() - sc["mH"][:, 0]) <= TOL * hmax).all()
+        # C = 2T d_T + T^2 d_TT: the chain rule adds 2<H>/T and subtracts it inside T^2 d_TT
+        cbound = TOL * (Cref[:, 0] + 4 * hmax / T_GRID)
+        assert (np.abs(C.cpu().numpy() - Cref[:, 0]) <= cbound).all()
         # chi at each T separately (h has one point): <M> = T d log Z/dh
         for a, t in enumerate(T_GRID):
             Ta = torch.tensor([t], device="cuda", dtype=torch.float64)
             ha = torch.tensor([h0], device="cuda", dtype=torch.float64, requires_grad=True)
             (dha,) = torch.autograd.grad(f(Ta, ha).sum(), ha, create_graph=True)
             chi = torch.autograd.grad((t * dha).sum(), ha)[0]
-            assert chi.item() == pytest.approx(chiref[a, 0], rel=1e-10)
+            assert chi.item() == pytest.approx(chiref[a, 0], rel=TOL)
         mom = api.moments(_dev_table(g), -S, N, T_GRID, [h0])
-        np.testing.assert_allclose(C.cpu().numpy(), mom["heat_capacity"][:, 0].cpu().numpy(), rtol=1e-10)
+        assert (np.abs(C.cpu().numpy() - mom["heat_capacity"][:, 0].cpu().numpy()) <= cbound).all()
 
 
 def test_second_derivative_in_couplings_raises(ag):
@@ -350,15 +364,17 @@ def test_torus6x6_bond_gradients_match_kaufman_and_sum_rule(api, ag):
             sel[a, c] = 1.0
             (gJ,) = torch.autograd.grad((f(T, h, J) * sel).sum(), J)
             gJ = gJ.cpu().numpy()
+            # each bond's sum over configurations of p s_i s_j / T: sum |W| g = 1/T
+            bound = TOL_SUM / t
             # edge-transitive torus at uniform J: every bond has the same gradient
-            np.testing.assert_allclose(gJ, gJ.mean(), rtol=1e-11)
+            assert (np.abs(gJ - gJ.mean()) <= 2 * bound).all()
             # sum rule: sum_b J_b d log Z/dJ_b = -<E>/T, with <E> from the oracle's exact table
             mE, _, _, _ = thermo.moments(gref, -72, 36, [t], [hh])
-            assert float((lat.bond_J * gJ).sum()) == pytest.approx(-mE[0, 0] / t, rel=1e-11)
+            assert abs(float((lat.bond_J * gJ).sum()) + mE[0, 0] / t) <= 72 * bound + TOL * 72 / t
             if hh == 0.0:
                 with mp.workdps(40):
                     dK = float(mp.diff(lambda Jv: closed_forms.kaufman_logz(6, 6, t / Jv), 1))
-                np.testing.assert_allclose(gJ, dK / lat.n_bonds, rtol=1e-10)
+                assert (np.abs(gJ - dK / lat.n_bonds) <= bound).all()
 
 
 def test_symmetric_backward_option_matches_full(ag):

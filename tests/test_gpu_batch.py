@@ -1,13 +1,21 @@
 """Batched persistent enumeration, batched moments and graph replay, against
-the oracle (bit-exact tables, FP64 moments within 1e-12)."""
+the oracle (bit-exact tables, FP64 log Z and moments within 1e-12).
+
+Every member of the batch256 workload is compared with an oracle table: the
+square tori with the transfer matrix, the triangular patches with the banded
+count, the 3x3x3 cubes with the brute force's stored tables
+(tests/golden/batch256_cubes.npz, written by an oracle-only script)."""
 import numpy as np
 import pytest
 import torch
 
+from conftest import load_cube_goldens
 from oracle import closed_forms, native, thermo
 from paper_1110_2561_amd import lattice as L
 
 pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -59,13 +67,41 @@ def test_small_batch_bit_exact(api, tune, symmetric):
         np.testing.assert_array_equal(plan.table(g_host, i).numpy(), _bf(lat))
 
 
-def test_batch256_parity(api):
-    lats = L.workload("batch256")["lattices"]
+@pytest.fixture(scope="module")
+def b256():
+    """The batch256 workload and the oracle's table of every member."""
+    w = L.workload("batch256")
+    cubes = load_cube_goldens()
+    refs = []
+    for i, lat in enumerate(w["lattices"]):
+        if lat.kind == "square_torus":
+            refs.append(native.tm_torus(*L.torus_coupling_grids(lat)))
+        elif lat.kind == "triangular_free":           # bandwidth <= 7: the banded count
+            refs.append(native.band_count(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J))
+        else:                                         # 3x3x3 cube: stored brute-force table
+            refs.append(cubes[i])
+    return w, refs
+
+
+def _check_moments(out, i, ref, lat, T, h, what):
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    lz = thermo.log_z(ref, -S, N, T, h)
+    mE, mM, C, chi = thermo.moments(ref, -S, N, T, h)
+    msg = f"{what}: member {i} ({lat.kind}, N={N})"
+    np.testing.assert_allclose(out["log_z"][i], lz, rtol=RTOL, atol=0, err_msg=msg)
+    np.testing.assert_allclose(out["mean_E"][i], mE, rtol=RTOL, atol=RTOL * max(S, 1), err_msg=msg)
+    np.testing.assert_allclose(out["mean_M"][i], mM, rtol=RTOL, atol=RTOL * N, err_msg=msg)
+    np.testing.assert_allclose(out["heat_capacity"][i], C, rtol=RTOL, atol=1e-300, err_msg=msg)
+    np.testing.assert_allclose(out["susceptibility"][i], chi, rtol=RTOL, atol=1e-300, err_msg=msg)
+
+
+def test_batch256_parity(api, b256):
+    w, refs = b256
+    lats = w["lattices"]
     plan = api.BatchPlan(lats)
     g = api.batch_enumerate(plan)
     torch.cuda.synchronize()
     g_host = g.cpu()
-    cubes = [i for i, l in enumerate(lats) if l.kind == "cubic_torus"][:6]
     for i, lat in enumerate(lats):
         t = plan.table(g_host, i).numpy()
         N = lat.n_spins
@@ -73,14 +109,20 @@ def test_batch256_parity(api):
         assert int(t.sum()) == 1 << N, i
         np.testing.assert_array_equal(t.sum(axis=0).astype(object), closed_forms.binomial_marginal(N))
         np.testing.assert_array_equal(t, t[:, ::-1])
-        # the oracle wherever it finishes in seconds
-        if lat.kind == "square_torus":
-            np.testing.assert_array_equal(t, native.tm_torus(*L.torus_coupling_grids(lat)))
-        elif lat.kind == "triangular_free":           # bandwidth <= 7: the banded count
-            np.testing.assert_array_equal(t, native.band_count(N, lat.bond_i, lat.bond_j, lat.bond_J))
-        elif i in cubes:
-            print(f"member {i}: {lat.kind} N={N} vs brute force", flush=True)
-            np.testing.assert_array_equal(t, _bf(lat))
+        # every member against the oracle, bit for bit
+        np.testing.assert_array_equal(t, refs[i], err_msg=f"member {i} ({lat.kind}, N={N})")
+
+
+def test_batch256_moments_match_oracle(api, b256):
+    # the GPU's own batched tables and batched moments on the workload's
+    # 64 x 3 grid, against the oracle's FP64 evaluation of the oracle tables
+    w, refs = b256
+    lats, T, h = w["lattices"], w["T"], w["h"]
+    plan = api.BatchPlan(lats)
+    g = api.batch_enumerate(plan)
+    out = {k: v.cpu().numpy() for k, v in api.batch_moments(plan, g, T, h).items()}
+    for i, lat in enumerate(lats):
+        _check_moments(out, i, refs[i], lat, T, h, "batched moments")
 
 
 def test_batch256_halved_equals_full(api):
@@ -122,16 +164,15 @@ def test_batch_moments_match_oracle(api):
         np.testing.assert_allclose(out["log_z"][i].cpu().numpy(), lz, rtol=1e-12, atol=1e-13)
         np.testing.assert_allclose(out["mean_E"][i].cpu().numpy(), mE, rtol=1e-12, atol=1e-12 * max(S, 1))
         np.testing.assert_allclose(out["mean_M"][i].cpu().numpy(), mM, rtol=1e-12, atol=1e-12 * N)
-        np.testing.assert_allclose(out["heat_capacity"][i].cpu().numpy(), C, rtol=1e-11, atol=1e-300)
-        np.testing.assert_allclose(out["susceptibility"][i].cpu().numpy(), chi, rtol=1e-11, atol=1e-300)
+        np.testing.assert_allclose(out["heat_capacity"][i].cpu().numpy(), C, rtol=RTOL, atol=1e-300)
+        np.testing.assert_allclose(out["susceptibility"][i].cpu().numpy(), chi, rtol=RTOL, atol=1e-300)
 
 
 @pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
-def test_graph_replays_equal_eager(api, symmetric):
-    lats = L.workload("batch256")["lattices"]
+def test_graph_replays_equal_eager(api, b256, symmetric):
+    w, refs = b256
+    lats, T, h = w["lattices"], w["T"], w["h"]
     plan = api.BatchPlan(lats)
-    T = np.linspace(0.5, 5.0, 64)
-    h = np.array([0.0, 0.1, 0.5])
     eager_g = api.batch_enumerate(plan)
     eager = api.batch_moments(plan, eager_g, T, h)
     torch.cuda.synchronize()
@@ -145,6 +186,12 @@ def test_graph_replays_equal_eager(api, symmetric):
         assert torch.equal(graph.g_all.cpu(), eager_g.cpu()), rep
         for k, v in eager.items():
             assert torch.equal(torch.nan_to_num(graph.outs[k], 1.5).cpu(), torch.nan_to_num(v, 1.5).cpu()), (rep, k)
+        if rep == 0:      # the replay's results against the oracle
+            g_host = graph.g_all.cpu()
+            outs = {k: v.cpu().numpy() for k, v in graph.outs.items()}
+            for i, lat in enumerate(lats):
+                np.testing.assert_array_equal(plan.table(g_host, i).numpy(), refs[i], err_msg=f"member {i}")
+                _check_moments(outs, i, refs[i], lat, T, h, "graph replay")
         # eager work between replays
         api.batch_enumerate(plan, out=eager_g)
         torch.cuda.synchronize()

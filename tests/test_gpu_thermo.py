@@ -2,7 +2,8 @@
 
 Tolerance: 1e-12 relative (FP64 log-sum-exp over <= 10^4 bins; both sides
 round differently only in summation order), absolute 1e-12 * N where the
-exact value is 0 (<M> at h = 0).
+exact value is 0 (<M> at h = 0).  C and chi are centred sums of non-negative
+terms, so the same bound holds for them.
 """
 import numpy as np
 import pytest
@@ -46,8 +47,48 @@ def test_logz_and_moments_match_oracle(api, name):
     np.testing.assert_allclose(out["log_z"].cpu().numpy(), ref_lz, rtol=RTOL, atol=0)
     np.testing.assert_allclose(out["mean_E"].cpu().numpy(), mE, rtol=RTOL, atol=RTOL * S)
     np.testing.assert_allclose(out["mean_M"].cpu().numpy(), mM, rtol=RTOL, atol=RTOL * N)
-    np.testing.assert_allclose(out["heat_capacity"].cpu().numpy(), C, rtol=1e-11, atol=1e-300)
-    np.testing.assert_allclose(out["susceptibility"].cpu().numpy(), chi, rtol=1e-11, atol=1e-300)
+    np.testing.assert_allclose(out["heat_capacity"].cpu().numpy(), C, rtol=RTOL, atol=1e-300)
+    np.testing.assert_allclose(out["susceptibility"].cpu().numpy(), chi, rtol=RTOL, atol=1e-300)
+
+
+def test_table_with_more_bins_than_the_lds_stage(api):
+    # A 22-spin triangular patch with 8 widely spaced couplings has ~8300
+    # nonzero bins, more than the 4096 the thermo kernels stage in LDS, so they
+    # read the dense table in place.  Enumerated on the GPU (bit-exact against
+    # the banded count), then log Z, moments and derivatives against the oracle.
+    from conftest import moment_scales
+    from oracle import grad
+    base = L.triangular_free(22, 5)
+    lat = L.triangular_free(22, 5, L.choice_couplings(base.n_bonds, 77, (-37, -11, 3, 23, -7, 13, 31, -19)))
+    g_ref = native.band_count(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J)
+    assert np.count_nonzero(g_ref) > 4096
+    plan = api.Plan(lat)
+    g = api.enumerate_g(plan)
+    np.testing.assert_array_equal(g.cpu().numpy(), g_ref)
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    T = np.linspace(0.5, 5.0, 24)
+    h = np.array([-1.0, 0.0, 0.3, 2.0, 5.0])
+    out = {k: v.cpu().numpy() for k, v in api.moments(g, -S, N, T, h).items()}
+    ref_lz = thermo.log_z(g_ref, -S, N, T, h)
+    mE, mM, C, chi = thermo.moments(g_ref, -S, N, T, h)
+    np.testing.assert_allclose(api.log_z(g, -S, N, T, h).cpu().numpy(), ref_lz, rtol=RTOL, atol=0)
+    np.testing.assert_allclose(out["log_z"], ref_lz, rtol=RTOL, atol=0)
+    np.testing.assert_allclose(out["mean_E"], mE, rtol=RTOL, atol=RTOL * S)
+    np.testing.assert_allclose(out["mean_M"], mM, rtol=RTOL, atol=RTOL * N)
+    np.testing.assert_allclose(out["heat_capacity"], C, rtol=RTOL, atol=1e-300)
+    np.testing.assert_allclose(out["susceptibility"], chi, rtol=RTOL, atol=1e-300)
+    d = {k: v.cpu().numpy() for k, v in api.logz_derivatives(g, -S, N, T, h).items()}
+    sc = moment_scales(g_ref, S, N, T, h)
+    for k, v in grad.log_z_derivatives(g_ref, -S, N, T, h).items():
+        assert (np.abs(d[k] - v) <= RTOL * sc[k]).all(), k
+    # the batched kernel reads it in place too
+    bp = api.BatchPlan([lat, L.square_torus(4, 4)])
+    gb = api.batch_enumerate(bp)
+    ob = {k: v.cpu().numpy() for k, v in api.batch_moments(bp, gb, T, h).items()}
+    np.testing.assert_array_equal(bp.table(gb.cpu(), 0).numpy(), g_ref)
+    np.testing.assert_allclose(ob["log_z"][0], ref_lz, rtol=RTOL, atol=0)
+    np.testing.assert_allclose(ob["heat_capacity"][0], C, rtol=RTOL, atol=1e-300)
+    np.testing.assert_allclose(ob["susceptibility"][0], chi, rtol=RTOL, atol=1e-300)
 
 
 def test_end_to_end_4x4_from_gpu_table(api):
