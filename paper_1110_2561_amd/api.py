@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from .lattice import Lattice
 
-__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_symmetric", "enumerate_range", "log_z", "moments", "per_spin",
+__all__ = ["Plan", "Tune", "enumerate_g", "enumerate_symmetric", "enumerate_range", "log_z", "moments",
            "IsingError",
            "logz_derivatives", "bin_weights", "bond_backward",
            "BatchPlan", "batch_enumerate", "batch_moments", "BatchGraph"]
@@ -88,6 +88,18 @@ class Plan:
             _lib.check(_lib.ising_bond_workspace(self._h, ctypes.byref(n)))
             self._bw_bytes = n.value
         return self._bw_bytes
+
+    def bond_workspace(self, device) -> torch.Tensor:
+        """The plan's backward workspace on `device`, allocated on first use and
+        kept.  Calls that use it are stream-ordered; calls on different streams
+        that overlap in time must pass workspaces of their own."""
+        device = torch.device(device)
+        cache = self.__dict__.setdefault("_ws", {})
+        ws = cache.get(device)
+        if ws is None:
+            ws = torch.empty(max(self.bond_workspace_bytes, 8), dtype=torch.uint8, device=device)
+            cache[device] = ws
+        return ws
 
     def close(self):
         if getattr(self, "_h", None):
@@ -176,28 +188,20 @@ def moments(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dic
     return outs
 
 
-def per_spin(m: dict, n_spins: int, T) -> dict:
-    """Intensive forms of the totals moments() returns: <E>/N, <M>/N, C/N,
-    chi/N, log Z / N, and the free energy per spin f = -T log Z / N (the
-    library's C and chi are totals over the N spins)."""
-    Tt = _grid(T, m["log_z"].device).reshape(-1, 1)
-    out = {k: m[k] / n_spins for k in ("log_z", "mean_E", "mean_M", "heat_capacity", "susceptibility")}
-    out["free_energy"] = -Tt * m["log_z"] / n_spins
-    return out
-
-
-def logz_derivatives(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None) -> dict:
+def logz_derivatives(g: torch.Tensor, e_min: int, n_spins: int, T, h, stream=None, second: bool = True) -> dict:
     """log Z and its first and second derivatives in (T, h), each [len(T), len(h)]
-    (ising_logz_derivatives): keys log_z, d_T, d_h, d_TT, d_Th, d_hh."""
+    (ising_logz_derivatives): keys log_z, d_T, d_h, d_TT, d_Th, d_hh; with
+    second=False only log_z, d_T and d_h (the kernel then skips its
+    second-moment pass)."""
     _check_dense(g)
     Tt, ht = _grid(T, g.device), _grid(h, g.device)
     shape = (Tt.numel(), ht.numel())
-    keys = ("log_z", "d_T", "d_h", "d_TT", "d_Th", "d_hh")
+    keys = ("log_z", "d_T", "d_h", "d_TT", "d_Th", "d_hh") if second else ("log_z", "d_T", "d_h")
     outs = {k: torch.empty(shape, dtype=torch.float64, device=g.device) for k in keys}
+    ptrs = [outs[k].data_ptr() if k in outs else None for k in ("log_z", "d_T", "d_h", "d_TT", "d_Th", "d_hh")]
     n_e, n_m = g.shape
     _lib.check(_lib.ising_logz_derivatives(g.data_ptr(), n_e, n_m, int(e_min), int(n_spins), Tt.data_ptr(),
-                                           Tt.numel(), ht.data_ptr(), ht.numel(),
-                                           *[outs[k].data_ptr() for k in keys], _stream_handle(stream)))
+                                           Tt.numel(), ht.data_ptr(), ht.numel(), *ptrs, _stream_handle(stream)))
     return outs
 
 
@@ -230,7 +234,7 @@ def bond_backward(plan: Plan, W: torch.Tensor, out: torch.Tensor | None = None, 
     nb = plan.lattice.n_bonds
     dJ = torch.empty(nb, dtype=torch.float64, device=W.device) if out is None else out
     _check_out(dJ, (nb,), W.device, "out")
-    ws = torch.empty(max(plan.bond_workspace_bytes, 8), dtype=torch.uint8, device=W.device)
+    ws = plan.bond_workspace(W.device)
     fn = _lib.ising_bond_backward_symmetric if symmetric else _lib.ising_bond_backward
     _lib.check(fn(plan.handle, W.data_ptr(), dJ.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
     return dJ

@@ -74,12 +74,21 @@ class _LogZ(torch.autograd.Function):
         go = go.to(torch.float64).contiguous()
         gT = gh = gJ = None
         if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
-            dT, dh = _LogZFirst.apply(T, h, model)
+            if torch.is_grad_enabled():
+                # building a graph for a double backward: the first derivatives
+                # as a differentiable function of (T, h)
+                dT, dh = _LogZFirst.apply(T, h, model)
+            else:
+                d = api.logz_derivatives(model.g, model.plan.e_min, model.plan.n_spins, T.detach(), h.detach(),
+                                         second=False)
+                dT, dh = d["d_T"], d["d_h"]
             gT = (go * dT).sum(dim=1) if ctx.needs_input_grad[0] else None
             gh = (go * dh).sum(dim=0) if ctx.needs_input_grad[1] else None
         if ctx.needs_input_grad[2]:
+            # the weight table is only read by the backward kernel that follows
+            # on the same stream, so the model's buffer is reused call to call
             W = api.bin_weights(model.g, model.plan.e_min, model.plan.n_spins, T.detach(), h.detach(), lz,
-                                go.detach())
+                                go.detach(), out=model.weights_buffer())
             gJ = api.bond_backward(model.plan, W, symmetric=model.symmetric_backward)
             if torch.is_grad_enabled():
                 gJ = _NotTwiceDifferentiable.apply(gJ, T, h, J)
@@ -94,6 +103,10 @@ class IsingLogZ:
     T and h are cast to float64 (differentiably).  With symmetric_backward the
     per-bond gradient walks half of the configurations (spin-flip symmetry,
     api.bond_backward(symmetric=True)); the default recomputes all of them.
+
+    Backward passes of one instance reuse its weight buffer and the plan's
+    workspace in stream order: backward passes that overlap in time on
+    different streams need instances of their own.
     """
 
     def __init__(self, lattice: Lattice, tune: api.Tune | None = None, symmetric_backward: bool = False):
@@ -102,9 +115,31 @@ class IsingLogZ:
         self.plan = api.Plan(lattice, tune)
         self.g = api.enumerate_g(self.plan)
         self._J = np.asarray(lattice.bond_J, dtype=np.float64)
+        self._J_dev = torch.as_tensor(self._J, dtype=torch.float64, device=self.g.device)
+        self._W = None
+        # (tensor, version counter) of the coupling tensor last checked against
+        # the lattice: checking costs a device-to-host copy, so a tensor is
+        # checked again only after an in-place change
+        self._checked = None
 
     def couplings(self, device="cuda", requires_grad: bool = True) -> torch.Tensor:
         return torch.tensor(self._J, dtype=torch.float64, device=device, requires_grad=requires_grad)
+
+    def weights_buffer(self) -> torch.Tensor:
+        """[n_e][n_m] FP64 device buffer for the backward's bin weights."""
+        if self._W is None:
+            self._W = torch.empty((self.plan.n_e, self.plan.n_m), dtype=torch.float64, device=self.g.device)
+        return self._W
+
+    def _check_couplings(self, J: torch.Tensor):
+        if J.shape != (self.lattice.n_bonds,) or J.dtype != torch.float64:
+            raise ValueError(f"J must be a float64 tensor of shape ({self.lattice.n_bonds},)")
+        seen = self._checked
+        if seen is not None and seen[0] is J and seen[1] == J._version:
+            return
+        if not np.array_equal(J.detach().cpu().numpy(), self._J):
+            raise ValueError("J must hold the lattice's integer couplings (the enumeration is exact for those)")
+        self._checked = (J, J._version)
 
     def __call__(self, T, h, J: torch.Tensor | None = None) -> torch.Tensor:
         dev = self.g.device
@@ -114,11 +149,9 @@ class IsingLogZ:
             raise ValueError("T and h must be 1-D tensors")
         T, h = T.to(device=dev, dtype=torch.float64), h.to(device=dev, dtype=torch.float64)   # differentiable casts
         if J is None:
-            J = torch.as_tensor(self._J, dtype=torch.float64, device=dev)
-        if J.shape != (self.lattice.n_bonds,) or J.dtype != torch.float64:
-            raise ValueError(f"J must be a float64 tensor of shape ({self.lattice.n_bonds},)")
-        if not np.array_equal(J.detach().cpu().numpy(), self._J):
-            raise ValueError("J must hold the lattice's integer couplings (the enumeration is exact for those)")
+            J = self._J_dev
+        else:
+            self._check_couplings(J)
         return _LogZ.apply(T, h, J, self)
 
 

@@ -179,18 +179,6 @@ def test_autotune_cache_key_names_the_batch_and_the_build():
     assert ka.split(":")[1] == autotune._library_tag()
 
 
-def test_per_spin_forms():
-    import torch
-
-    from paper_1110_2561_amd import api
-    T = [0.5, 2.0]
-    m = {k: torch.arange(1.0, 5.0, dtype=torch.float64).reshape(2, 2)
-         for k in ("log_z", "mean_E", "mean_M", "heat_capacity", "susceptibility")}
-    p = api.per_spin(m, 4, T)
-    assert torch.equal(p["heat_capacity"], m["heat_capacity"] / 4)
-    assert torch.allclose(p["free_energy"], -torch.tensor([[0.5], [2.0]], dtype=torch.float64) * m["log_z"] / 4)
-
-
 def test_bench_refuses_more_than_one_gpu():
     # the library has no multi-GPU path; bench.py says so and exits non-zero
     import subprocess
