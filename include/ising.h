@@ -210,6 +210,21 @@ ising_status ising_bond_backward(const ising_plan *plan, const double *W_dev, do
 ising_status ising_bond_backward_symmetric(const ising_plan *plan, const double *W_dev, double *dJ_dev,
                                            void *workspace, size_t workspace_bytes, void *stream);
 
+/* ising_bond_backward without a workspace, for callers that cannot allocate
+ * device memory at the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  It calls no allocating routine:
+ * the per-block partial sums go to a static device array of the library
+ * (4 MiB, at most 1024 blocks x 512 bond pairs; each device that runs it
+ * holds its copy until the process ends), and the plan's device tables must
+ * already be on the current device: one ising_bond_backward or
+ * ising_bond_backward_symmetric call there uploads them, otherwise the call
+ * fails with ISING_EINVAL.  Calls on one device share the array: calls that
+ * overlap in time on one device race (serialise them on one stream).
+ * W_dev, dJ_dev and the result are as in ising_bond_backward (the same
+ * kernels in the same order, so the values are identical). */
+ising_status ising_bond_backward_noalloc(const ising_plan *plan, const double *W_dev, double *dJ_dev,
+                                         void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batches: many lattices of uneven size in one persistent launch.          */
 /* ------------------------------------------------------------------------ */

@@ -436,8 +436,10 @@ __global__ __launch_bounds__(kFinishThreads) void k_bond_finish(const BondTables
     if (pair_of_bond[b] == p) dJ[b] = total;
 }
 
-// {DevPlan, BondTables, pair_of_bond} of the backward on `device` (lazy).
-static void *bond_device_tables(ising_plan *p, int device, ising_status *st) {
+// {DevPlan, BondTables, pair_of_bond} of the backward on `device`: uploaded
+// on first use when `may_allocate`, else only looked up (null with
+// ISING_EINVAL if not there yet).
+static void *bond_device_tables(ising_plan *p, int device, bool may_allocate, ising_status *st) {
   *st = ISING_OK;
   if (device < 0 || device >= kMaxDevices) {
     *st = fail(ISING_EUNSUPPORTED, "device index out of range");
@@ -445,6 +447,12 @@ static void *bond_device_tables(ising_plan *p, int device, ising_status *st) {
   }
   BondPlan *bp = p->bond;
   std::lock_guard<std::mutex> lk(p->mu);
+  if (!bp->dev_copy[device] && !may_allocate) {
+    *st = fail(ISING_EINVAL, "the plan's backward tables are not on device " + std::to_string(device) +
+                                 " yet: one ising_bond_backward or ising_bond_backward_symmetric call there "
+                                 "uploads them");
+    return nullptr;
+  }
   if (!bp->dev_copy[device]) {
     const size_t bytes = sizeof(DevPlan) + sizeof(BondTables) + bp->pair_of_bond.size() * sizeof(int32_t);
     std::vector<char> host(bytes);
@@ -512,6 +520,54 @@ static ising_status bond_dispatch(int tile, int n_classes, const DevPlan *dP, co
   return fail(ISING_EUNSUPPORTED, "tile bits or class count out of range");
 }
 
+// One backward launch: device tables, work range and grid.
+struct BondLaunch {
+  const DevPlan *dP = nullptr;
+  const BondTables *dT = nullptr;
+  const int32_t *dmap = nullptr;
+  uint64_t n_chunks = 0, t_begin = 0, n_tasks = 0;
+  int grid = 0;
+  bool mirror = false;
+};
+
+static ising_status bond_setup(const ising_plan *pc, bool halve, bool may_allocate, BondLaunch *L) {
+  ising_plan *p = const_cast<ising_plan *>(pc);  // only the lazy device copy is written
+  const BondPlan *bp = pc->bond;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  ising_status st;
+  char *tables = static_cast<char *>(bond_device_tables(p, dev, may_allocate, &st));
+  if (!tables) return st;
+  L->dP = reinterpret_cast<const DevPlan *>(tables);
+  L->dT = reinterpret_cast<const BondTables *>(tables + sizeof(DevPlan));
+  L->dmap = reinterpret_cast<const int32_t *>(tables + sizeof(DevPlan) + sizeof(BondTables));
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  L->n_chunks = uint64_t(1) << (bp->geo.n - bp->geo.inner);
+  static_assert(kBwWaves * kWave == 1 << kLaneBits, "a block walks 2^kLaneBits chunks per task");
+  const uint64_t block = uint64_t(kBwWaves) * kWave;
+  L->n_tasks = (L->n_chunks + block - 1) / block;
+  // Halving needs the top spin to be a task bit (at least two tasks, both
+  // powers of two): tasks [n_tasks/2, n_tasks) are the configurations with
+  // it up.  Smaller lattices take the full walk, with the same result.
+  L->mirror = halve && L->n_tasks >= 2;
+  L->t_begin = L->mirror ? L->n_tasks / 2 : 0;
+  L->grid = int(std::min<uint64_t>({L->n_tasks - L->t_begin, uint64_t(cus), uint64_t(kMaxBwBlocks)}));
+  return ISING_OK;
+}
+
+static ising_status bond_launch(const ising_plan *pc, const BondLaunch &L, const double *W_dev, double *partial,
+                                double *dJ_dev, hipStream_t s) {
+  const BondPlan *bp = pc->bond;
+  ising_status st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, L.dP, L.dT, W_dev, L.n_chunks, L.t_begin,
+                                  L.n_tasks, L.mirror ? 1 : 0, L.grid, partial, s);
+  if (st != ISING_OK) return st;
+  hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(bp->tables.n_pairs)), dim3(kFinishThreads), 0, s, L.dT, L.dmap,
+                     partial, L.grid, dJ_dev);
+  HIP_TRY(hipGetLastError());
+  return ISING_OK;
+}
+
 static ising_status bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev, void *workspace,
                                   size_t workspace_bytes, bool halve, void *stream) {
   if (!pc) return fail(ISING_EINVAL, "plan is NULL");
@@ -525,35 +581,62 @@ static ising_status bond_backward(const ising_plan *pc, const double *W_dev, dou
   if (workspace_bytes < need)
     return fail(ISING_EINVAL, "workspace of " + std::to_string(workspace_bytes) + " bytes; " +
                                   std::to_string(need) + " needed");
-  ising_plan *p = const_cast<ising_plan *>(pc);  // only the lazy device copy is written
+  BondLaunch L;
+  st = bond_setup(pc, halve, true, &L);
+  if (st != ISING_OK) return st;
+  return bond_launch(pc, L, W_dev, static_cast<double *>(workspace), dJ_dev, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free form: the per-block partial sums live in a static device
+// array instead of a caller workspace.  Each device that runs it holds its
+// own copy of the array until the process ends; calls on one device share
+// it, so calls that overlap in time on one device race.  Every block writes
+// all n_pairs entries of its row before the finishing kernel reads them, so
+// nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kScratchDoubles = size_t(kMaxBwBlocks) * size_t(kMaxPairs);   // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch[kMaxDevices];
+
+// Device address of this device's copy of `scratch` (looked up once per
+// device; the host-side name is only a stand-in for the symbol).
+static ising_status scratch_on_device(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ISING_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(ISING_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch[dev];
+  return ISING_OK;
+}
+
+static ising_status bond_backward_noalloc(const ising_plan *pc, const double *W_dev, double *dJ_dev, void *stream) {
+  if (!pc) return fail(ISING_EINVAL, "plan is NULL");
+  const BondPlan *bp = pc->bond;
+  if (bp->status != ISING_OK) return fail(bp->status, bp->error);
+  if (pc->n_bonds == 0) return ISING_OK;
+  if (!W_dev || !dJ_dev) return fail(ISING_EINVAL, "W_dev or dJ_dev is NULL");
+  BondLaunch L;
+  ising_status st = bond_setup(pc, false, false, &L);
+  if (st != ISING_OK) return st;
+  const size_t need = size_t(L.grid) * size_t(bp->tables.n_pairs);
+  if (need > kScratchDoubles)
+    return fail(ISING_ERANGE, "partial sums of " + std::to_string(need) + " doubles exceed the " +
+                                  std::to_string(kScratchDoubles) + " of the static scratch array");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  char *tables = static_cast<char *>(bond_device_tables(p, dev, &st));
-  if (!tables) return st;
-  const DevPlan *dP = reinterpret_cast<const DevPlan *>(tables);
-  const BondTables *dT = reinterpret_cast<const BondTables *>(tables + sizeof(DevPlan));
-  const int32_t *dmap = reinterpret_cast<const int32_t *>(tables + sizeof(DevPlan) + sizeof(BondTables));
-  int cus = 0;
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const uint64_t n_chunks = uint64_t(1) << (bp->geo.n - bp->geo.inner);
-  static_assert(kBwWaves * kWave == 1 << kLaneBits, "a block walks 2^kLaneBits chunks per task");
-  const uint64_t block = uint64_t(kBwWaves) * kWave;
-  const uint64_t n_tasks = (n_chunks + block - 1) / block;
-  // Halving needs the top spin to be a task bit (at least two tasks, both
-  // powers of two): tasks [n_tasks/2, n_tasks) are the configurations with
-  // it up.  Smaller lattices take the full walk, with the same result.
-  const bool mirror = halve && n_tasks >= 2;
-  const uint64_t t_begin = mirror ? n_tasks / 2 : 0;
-  const int grid = int(std::min<uint64_t>({n_tasks - t_begin, uint64_t(cus), uint64_t(kMaxBwBlocks)}));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  double *partial = static_cast<double *>(workspace);
-  st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, dP, dT, W_dev, n_chunks, t_begin, n_tasks, mirror ? 1 : 0,
-                     grid, partial, s);
+  double *partial = nullptr;
+  st = scratch_on_device(dev, &partial);
   if (st != ISING_OK) return st;
-  hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(bp->tables.n_pairs)), dim3(kFinishThreads), 0, s, dT, dmap,
-                     partial, grid, dJ_dev);
-  HIP_TRY(hipGetLastError());
-  return ISING_OK;
+  return bond_launch(pc, L, W_dev, partial, dJ_dev, static_cast<hipStream_t>(stream));
 }
 
 }  // namespace ising
@@ -568,4 +651,9 @@ extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *
 extern "C" ising_status ising_bond_backward_symmetric(const ising_plan *pc, const double *W_dev, double *dJ_dev,
                                                       void *workspace, size_t workspace_bytes, void *stream) {
   return bond_backward(pc, W_dev, dJ_dev, workspace, workspace_bytes, true, stream);
+}
+
+extern "C" ising_status ising_bond_backward_noalloc(const ising_plan *pc, const double *W_dev, double *dJ_dev,
+                                                    void *stream) {
+  return bond_backward_noalloc(pc, W_dev, dJ_dev, stream);
 }
