@@ -204,11 +204,34 @@ ising_status ising_bond_backward(const ising_plan *plan, const double *W_dev, do
  * over those whose top spin (in the plan's order) is up, each weighted by
  * W(E, M) + W(E, -M); the paper's closing section suggests using such
  * symmetries.  About half the work; equal to ising_bond_backward up to FP64
- * summation order.  Lattices with fewer than tile_bits + 10 spins take the
- * full walk (the half is not a whole number of the walk's tasks there).
+ * summation order.  Lattices of at most tile_bits + 20 spins take the full
+ * walk (their top spin is not among the spins every block walks in turn).
  * Arguments, workspace and errors as ising_bond_backward. */
 ising_status ising_bond_backward_symmetric(const ising_plan *plan, const double *W_dev, double *dJ_dev,
                                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* The whole backward of log Z in one call: the gradient of a loss
+ * L = sum_{a,b} G[a][b] log Z(T_a, h_b) (Eq. (2) for the plan's lattice) with
+ * respect to the temperatures, the fields and the couplings, from the plan's
+ * table g_dev (as ising_enumerate wrote it):
+ *   grad_T[a] = sum_b G[a][b] <H>_ab / T_a^2,   grad_h[b] = sum_a G[a][b] <M>_ab / T_a
+ *   (the averages in one pass over the bins with the given log Z as
+ *   normaliser, <H> = sum p H / sum p, p = g exp(-(E - hM)/T - log Z); then
+ *   contracted with G, each sum in index order),
+ *   grad_J[k] = the ising_bond_backward sum of bond k with W = ising_bin_weights(G)
+ *   (its halved form ising_bond_backward_symmetric when `symmetric` is nonzero).
+ * T_dev[nT], h_dev[nh], logz_dev and G_dev [nT][nh] are FP64 device arrays
+ * (logz as ising_logz returns it for the same table and grid).  Outputs are
+ * FP64 device arrays of nT, nh and n_bonds entries; any may be NULL, and that
+ * part is skipped (grad_J needs a plan the per-bond backward supports).
+ * workspace: device memory of at least ising_logz_backward_workspace bytes,
+ * used only in the call's stream order.  All kernels are issued on `stream`
+ * in one call, with no host synchronisation. */
+ising_status ising_logz_backward_workspace(const ising_plan *plan, int32_t nT, int32_t nh, size_t *bytes);
+ising_status ising_logz_backward(const ising_plan *plan, const uint64_t *g_dev, const double *T_dev, int32_t nT,
+                                 const double *h_dev, int32_t nh, const double *logz_dev, const double *G_dev,
+                                 double *grad_T, double *grad_h, double *grad_J, int32_t symmetric,
+                                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* ising_bond_backward without a workspace, for callers that cannot allocate
  * device memory at the call (code under HIP graph capture, tight serving

@@ -69,6 +69,10 @@ ising_bond_workspace = _sig("ising_bond_workspace", i32, vp, ctypes.POINTER(ctyp
 ising_bond_backward = _sig("ising_bond_backward", i32, vp, vp, vp, vp, ctypes.c_size_t, vp)
 ising_bond_backward_symmetric = _sig("ising_bond_backward_symmetric", i32, vp, vp, vp, vp, ctypes.c_size_t, vp)
 ising_bond_backward_noalloc = _sig("ising_bond_backward_noalloc", i32, vp, vp, vp, vp)
+ising_logz_backward_workspace = _sig("ising_logz_backward_workspace", i32, vp, i32, i32,
+                                     ctypes.POINTER(ctypes.c_size_t))
+ising_logz_backward = _sig("ising_logz_backward", i32, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, i32, vp,
+                           ctypes.c_size_t, vp)
 i64p = ctypes.POINTER(ctypes.c_int64)
 ising_batch_plan_create = _sig("ising_batch_plan_create", i32, ctypes.POINTER(ising_lattice), i32,
                                ctypes.POINTER(ising_tune), ctypes.POINTER(vp))

@@ -16,7 +16,7 @@ from .lattice import Lattice
 
 __all__ = ["Plan", "Tune", "enumerate_g", "enumerate_symmetric", "enumerate_range", "log_z", "moments",
            "IsingError",
-           "logz_derivatives", "bin_weights", "bond_backward",
+           "logz_derivatives", "bin_weights", "bond_backward", "logz_backward",
            "BatchPlan", "batch_enumerate", "batch_moments", "BatchGraph"]
 
 IsingError = _lib.IsingError
@@ -238,6 +238,40 @@ def bond_backward(plan: Plan, W: torch.Tensor, out: torch.Tensor | None = None, 
     fn = _lib.ising_bond_backward_symmetric if symmetric else _lib.ising_bond_backward
     _lib.check(fn(plan.handle, W.data_ptr(), dJ.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
     return dJ
+
+
+def logz_backward(plan: Plan, g: torch.Tensor, T: torch.Tensor, h: torch.Tensor, logz: torch.Tensor,
+                  grad: torch.Tensor, want=(True, True, True), symmetric: bool = False, stream=None):
+    """(dL/dT, dL/dh, dL/dJ) of L = sum(grad * log Z) for the plan's lattice in
+    one library call (ising_logz_backward); an entry is None where `want` is
+    false.  T, h: 1-D float64 device tensors; logz, grad: [len(T), len(h)]
+    float64 device tensors; g: the plan's table.  The workspace is kept on the
+    plan (stream-ordered reuse)."""
+    _check_table(plan, g)
+    dev = g.device
+    Tt, ht = _grid(T, dev), _grid(h, dev)
+    nT, nh = Tt.numel(), ht.numel()
+    lz = logz if logz.is_contiguous() else logz.contiguous()
+    G = grad if grad.is_contiguous() else grad.contiguous()
+    if lz.dtype != torch.float64 or G.dtype != torch.float64 or lz.shape != (nT, nh) or G.shape != (nT, nh):
+        raise ValueError(f"logz and grad must be float64 tensors of shape {(nT, nh)}")
+    cache = plan.__dict__.setdefault("_lb", {})
+    key = (dev, nT, nh)
+    ws = cache.get(key)
+    if ws is None:
+        n = ctypes.c_size_t()
+        _lib.check(_lib.ising_logz_backward_workspace(plan.handle, nT, nh, ctypes.byref(n)))
+        ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        cache[key] = ws
+    gT = torch.empty(nT, dtype=torch.float64, device=dev) if want[0] else None
+    gh = torch.empty(nh, dtype=torch.float64, device=dev) if want[1] else None
+    gJ = torch.empty(plan.lattice.n_bonds, dtype=torch.float64, device=dev) if want[2] else None
+    _lib.check(_lib.ising_logz_backward(plan.handle, g.data_ptr(), Tt.data_ptr(), nT, ht.data_ptr(), nh,
+                                        lz.data_ptr(), G.data_ptr(), gT.data_ptr() if gT is not None else None,
+                                        gh.data_ptr() if gh is not None else None,
+                                        gJ.data_ptr() if gJ is not None else None, int(symmetric), ws.data_ptr(),
+                                        ws.numel(), _stream_handle(stream)))
+    return gT, gh, gJ
 
 
 # ---------------------------------------------------------------------------

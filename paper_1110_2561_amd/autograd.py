@@ -72,19 +72,20 @@ class _LogZ(torch.autograd.Function):
         T, h, J, lz = ctx.saved_tensors
         model = ctx.model
         go = go.to(torch.float64).contiguous()
+        need = ctx.needs_input_grad[:3]
+        if not torch.is_grad_enabled():
+            # no graph to build: the whole backward in one library call
+            gT, gh, gJ = api.logz_backward(model.plan, model.g, T.detach(), h.detach(), lz, go, want=need,
+                                           symmetric=model.symmetric_backward)
+            return gT, gh, gJ, None
         gT = gh = gJ = None
-        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
-            if torch.is_grad_enabled():
-                # building a graph for a double backward: the first derivatives
-                # as a differentiable function of (T, h)
-                dT, dh = _LogZFirst.apply(T, h, model)
-            else:
-                d = api.logz_derivatives(model.g, model.plan.e_min, model.plan.n_spins, T.detach(), h.detach(),
-                                         second=False)
-                dT, dh = d["d_T"], d["d_h"]
-            gT = (go * dT).sum(dim=1) if ctx.needs_input_grad[0] else None
-            gh = (go * dh).sum(dim=0) if ctx.needs_input_grad[1] else None
-        if ctx.needs_input_grad[2]:
+        if need[0] or need[1]:
+            # building a graph for a double backward: the first derivatives as
+            # a differentiable function of (T, h)
+            dT, dh = _LogZFirst.apply(T, h, model)
+            gT = (go * dT).sum(dim=1) if need[0] else None
+            gh = (go * dh).sum(dim=0) if need[1] else None
+        if need[2]:
             # the weight table is only read by the backward kernel that follows
             # on the same stream, so the model's buffer is reused call to call
             W = api.bin_weights(model.g, model.plan.e_min, model.plan.n_spins, T.detach(), h.detach(), lz,

@@ -12,51 +12,63 @@
 namespace ising {
 
 constexpr int kMaxPairs = 512;      // distinct bond pairs the per-bond backward handles
-constexpr int kBwMid = 4;           // middle bits of the backward walk (at most)
-constexpr int kBwWaves = 8;         // waves per block of the backward kernel
+constexpr int kBwMid = 2;           // middle bits of the backward walk (at most)
+constexpr int kBwWaves = 16;        // waves per block of the backward kernel
 constexpr int kMaxBwBlocks = 1024;  // blocks whose partial sums the workspace holds
+constexpr int kBlockBits = 8;       // block bits when the lattice has them: 256 blocks, one per CU
 
-constexpr int kLaneBits = 9;        // log2(kBwWaves * kWave): chunk bits fixed for a thread
+constexpr int kLaneBits = 10;       // log2(kBwWaves * kWave): chunk-offset bits fixed for a thread
 constexpr int kInner = kMaxTile + kBwMid;   // inner bits (tile + middle) at most
+constexpr int kRound = 8;           // values per wave in one LDS round of the final reduction
 
-// Where each distinct bond pair of the lattice sits in the backward walk, by
-// the kind of its two bits (bit positions of the backward geometry: tile
-// [0, TJ), middle [TJ, k = TJ + mj), then the prefix, whose first kLaneBits
-// bits are fixed for a thread ("lane-fixed", the chunk's offset in its task)
-// and the rest are the same for the whole block in one task ("task" bits)).
-// Per-lane running sums accumulate over all of a thread's chunks.  Pairs whose
-// sign pattern is fixed per thread are reduced once at the end; pairs with a
-// task bit are reduced per task, as differences of the cumulative wave sums.
+// Where the spins sit in the backward walk (bit positions of the plan's
+// order):
+//   [0, TJ)              tile: an independent set, walked per block of 2^TJ
+//                        configurations with constant address deltas;
+//   [TJ, k = TJ + mj)    middle bits, walked between tile blocks;
+//   [k, k + L)           offset bits: the thread's chunk offset (fixed per thread);
+//   [k + L, k + L + s)   block bits: the block index (fixed per block);
+//   [k + L + s, N)       hi bits: every block walks all their states in Gray
+//                        order, one chunk per thread per state, so the next
+//                        chunk differs from the last in a single spin.
+// Each thread keeps running sums over all it has walked: W, W s_a for every
+// inner bit a, W s_t s_m (tile-middle) and W s_m1 s_m2 (middle-middle).  A
+// pair whose sign pattern never changes for a thread (both bits inner,
+// offset or block bits) is read from them at the end.  A pair (a, p) with a
+// hi bit p takes, by summation by parts over the walk, s_p(end) times the
+// final running sum minus, at every flip of p, the change of s_p times the
+// running sum at that moment: one wave reduction per partner of the flipped
+// bit per chunk.
 struct BondTables {
   int32_t n_pairs;       // distinct bond pairs
   int32_t mj;            // middle bits
   int32_t rw;            // copies of the FP64 weight table in LDS
   int32_t wt_bytes;      // LDS bytes of the weight table (all copies)
   int32_t n_bonds;       // input bonds (pair_of_bond entries after this struct)
-  int32_t n_ltg;         // lane-fixed bits with task-bit partners
-  int32_t n_ll, n_tt;    // lane-fixed / lane-fixed and task / task pairs
+  int32_t s_bits;        // block bits: the grid has 2^s_bits blocks
+  int32_t n_hi;          // hi bits
+  int32_t n_offsets;     // chunk offsets that exist: min(2^L, 2^(N - k))
+  int32_t acc_bytes;     // LDS bytes of the per-wave pair accumulators (the table follows)
+  int32_t n_end_outer;   // end pairs with no inner bit
   int16_t qpair[kBwMid][kMaxTile];          // tile t - middle m pair, or -1
-  int16_t m2pair[6];                        // middle pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3), or -1
-  int16_t it_start[kInner + 1];             // inner a - task b, by a: [it_start[a], it_start[a+1])
-  int16_t it_pair[kMaxPairs];
-  uint8_t it_bit[kMaxPairs];
-  int16_t il_start[kInner + 1];             // inner a - lane-fixed b, by a
-  int16_t il_pair[kMaxPairs];
-  uint8_t il_bit[kMaxPairs];
-  uint8_t ltg_a[kLaneBits];                 // lane-fixed a - task b, grouped by a
-  int16_t ltg_start[kLaneBits + 1];
-  int16_t lt_pair[kMaxPairs];
-  uint8_t lt_bit[kMaxPairs];
-  int16_t ll_pair[kMaxPairs];               // lane-fixed a - lane-fixed b
-  uint8_t ll_a[kMaxPairs], ll_b[kMaxPairs];
-  int16_t tt_pair[kMaxPairs];               // task a - task b
-  uint8_t tt_a[kMaxPairs], tt_b[kMaxPairs];
-  uint16_t lane_chunk[kBwWaves * kWave];    // thread -> chunk offset within a task (a permutation)
+  int16_t m2pair;                           // middle pair (0, 1), or -1
+  int16_t pad0;
+  // end pairs with an inner bit a and a non-inner bit b, by a: [end_start[a], end_start[a+1])
+  int16_t end_start[kInner + 1];
+  int16_t end_pair[kMaxPairs];
+  uint8_t end_b[kMaxPairs];
+  // end pairs of two non-inner bits
+  int16_t eo_pair[kMaxPairs];
+  uint8_t eo_a[kMaxPairs], eo_b[kMaxPairs];
+  // pairs with hi bit j: inner partners by partner bit, others in a list
+  int16_t hp_inner[kMaxSpins][kInner];      // pair of (inner a, hi bit j), or -1
+  int16_t hp_start[kMaxSpins + 1];          // non-inner partners of hi bit j
+  int16_t hp_pair[2 * kMaxPairs];           // (a pair of two hi bits is listed under both)
+  uint8_t hp_a[2 * kMaxPairs];
+  // byte change of the tile delta i when bit b (>= TJ) flips up
+  int32_t kbit[kMaxSpins][kMaxTile];
+  uint16_t lane_chunk[kBwWaves * kWave];    // thread -> chunk offset (a permutation)
 };
-
-// LDS doubles per wave for the previous cumulative wave sums of the per-task
-// reductions: one per inner bit, per lane-fixed group, and for the total.
-constexpr int kPrevSlots = kInner + kLaneBits + 1;
 
 // Host-side backward plan, owned by its ising_plan.
 struct BondPlan {

@@ -6,35 +6,34 @@
 // product of every configuration; the enumeration is recomputed here in the
 // same Gray order as the forward walk, with FP64 sums in place of counts.
 //
-// Per lane and chunk (prefix fixed; k = tile + mj inner bits, mj <= 4; which
-// chunk of a task a thread takes is a planner table chosen so that lanes
-// sharing a weight-table copy read different LDS banks):
+// Bit layout (bond.h): tile, middle, offset (fixed per thread), block (fixed
+// per block) and hi bits.  A thread walks one chunk (tile + middle) per state
+// of the hi bits, which every block visits in Gray order, so the next chunk's
+// first configuration differs from the last one's in one middle or tile spin
+// (back to the chunk's start) and one hi spin: two incremental flips instead
+// of a fresh set-up.
 //   * the tile walk (2^TJ configurations, only tile bits flip, fully
 //     unrolled) reads W of each configuration from an LDS copy of the table
 //     (one ds_read_b64 on the same running address as the forward's
 //     histogram add).  The sums of W over the configurations with tile spin
-//     i up come from groups of 8 configurations: an add tree of the group
-//     gives tile bits 0-2 (up on fixed positions of the group), and higher
-//     tile bits, which flip only between groups, use a prefix-sum trick on
-//     the running sum of group totals.  Which spin flips, and which way, is a
-//     compile-time fact of the unrolled Gray sequence, so a configuration
-//     costs one load, one integer add and about two FP64 adds.
-//   * per tile block (walk) q the sums S_q = sum W and Y_q,i = sum W s_i are
-//     folded into the lane's running totals: sum W, sum W s_t, sum W s_m,
-//     sum W s_t s_m, sum W s_m1 s_m2 (s_m, the middle spins, are fixed within
-//     a block).  They run over all of the lane's chunks, never reset.
-//   * every coupled pair takes its sum from one of these (tile-middle,
-//     middle-middle), from sum W s_a times the sign of a prefix spin b
-//     (inner-prefix pairs), or from sum W times s_a s_b (both in the prefix).
-//     A thread's chunks share their low 9 bits (the block has 512 threads),
-//     so prefix spins there are fixed per thread; the rest ("task" bits) are
-//     the same for the whole block within one task.  Pairs with no task bit
-//     are summed over the wave once, at the end; the others after every task,
-//     from the growth of the wave totals they need (about a dozen per task
-//     rather than one per pair).  Wave sums use a DPP tree and go to per-wave
-//     LDS accumulators; blocks write per-pair partial sums and a second
-//     kernel adds them in a fixed order and scatters them to the input bonds.
-//     Every sum runs in a fixed order, so results are reproducible.
+//     i up come from groups of 4 configurations: tile bits 0-1 are up on
+//     fixed positions of a group, so their sums are nodes of the group's add
+//     tree; higher tile bits, which flip only between groups, use a
+//     prefix-sum trick on the running sum of group totals.  Which spin
+//     flips, and which way, is a compile-time fact of the unrolled Gray
+//     sequence, so a configuration costs one load, one integer add and two
+//     FP64 adds.
+//   * after each tile block the block's sums are folded into the thread's
+//     running sums: W, W s_a (every inner bit a), W s_t s_m, W s_m1 s_m2.
+//   * pairs whose sign pattern is fixed for a thread are read from the
+//     running sums at the end; a pair with a hi bit p also gets, at every
+//     flip of p, -(change of s_p) times the running sums at that moment
+//     (summation by parts over the walk), one wave reduction (DPP tree) per
+//     partner of the flipped bit.  The final reduction goes through LDS in
+//     rounds of 8 values per wave.  Per-wave accumulators in LDS, per-block
+//     partial sums, and a second kernel that adds the blocks in a fixed order
+//     and scatters the totals to the input bonds: every sum runs in a fixed
+//     order, so results are reproducible.
 // The tile is an independent set of the coupling graph, so there are no
 // tile-tile pairs.
 #include <hip/hip_runtime.h>
@@ -59,47 +58,41 @@ __device__ __forceinline__ double lds_f64(const char *base, uint32_t byte_addr) 
   return *reinterpret_cast<const double *>(base + byte_addr);
 }
 
-// One tile block of 2^TJ configurations: sw = sum of W, U[i] = sum of W over
-// the configurations with tile spin i up.  Odd blocks start with the top tile
-// bit set (reflected Gray code), so the tile state at step t is
+// Tile state at step t of a block of 2^TJ configurations.  Odd blocks start
+// with the top tile bit set (reflected Gray code), so the state is
 // gray(t) ^ (ODD ? top : 0).
 template <int TJ, bool ODD>
 __host__ __device__ constexpr uint32_t tile_state(int t) {
   return uint32_t(t ^ (t >> 1)) ^ (ODD ? (1u << (TJ - 1)) : 0u);
 }
 
-// Tile blocks of TJ >= 3 bits, in groups of 8 configurations (the low three
-// tile bits): inside a group, tile bits 0-2 are up on fixed position sets
-// ({1,2,5,6}, {2,3,4,5}, {4..7} or {0..3}, or their complements for the top
-// bit of an odd block), so their sums come from a small add tree of the
-// group (pairs, quads, total); higher tile bits flip only between groups and
-// use the prefix-sum trick on the running sum of group totals (subtract it
-// when the spin goes up, add it when it goes down, add the total at the end
-// if still up).  About two FP64 adds per configuration, with a dependent
-// chain of one add per group instead of one per configuration.
+// Sum of W over the configurations of group g (4 configurations) with tile
+// bit b up, from the group's add tree (pairs P01, P23, total G).
 template <int TJ, bool ODD>
-__device__ __forceinline__ double group_bit_sum(int g, int b, const double (&w)[8], double P23, double P45,
-                                                double Q0, double Q1, double G) {
+__device__ __forceinline__ double group_bit_sum(int g, int b, const double (&w)[4], double P01, double P23,
+                                                double G) {
   uint32_t mask = 0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) mask |= ((tile_state<TJ, ODD>(8 * g + u) >> b) & 1u) << u;
+  for (int u = 0; u < 4; ++u) mask |= ((tile_state<TJ, ODD>(4 * g + u) >> b) & 1u) << u;
   switch (mask) {
-    case 0x66: return (w[1] + w[2]) + (w[5] + w[6]);
-    case 0x99: return G - ((w[1] + w[2]) + (w[5] + w[6]));
-    case 0x3c: return P23 + P45;
-    case 0xc3: return G - (P23 + P45);
-    case 0xf0: return Q1;
-    case 0x0f: return Q0;
+    case 0x6: return w[1] + w[2];
+    case 0x9: return w[0] + w[3];
+    case 0xc: return P23;
+    case 0x3: return P01;
+    case 0xf: return G;
+    case 0x0: return 0.0;
     default: {   // not reached for the reflected Gray code; kept general
       double acc = 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 4; ++u)
         if ((mask >> u) & 1u) acc += w[u];
       return acc;
     }
   }
 }
 
+// One tile block of 2^TJ configurations: sw = sum of W, U[i] = sum of W over
+// the configurations with tile spin i up.
 template <int TJ, bool ODD>
 __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ], const char *wt, double &sw,
                                             double (&U)[TJ]) {
@@ -109,41 +102,33 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
   for (int i = 0; i < TJ; ++i) U[i] = 0.0;
   sw = 0.0;
   if constexpr (TJ >= 3) {
-    constexpr int kGroups = kN / 8;
-    // W of a group is loaded one group ahead of its sums.
-    double w[2][8];
+    constexpr int kGroups = kN / 4;
 #pragma unroll
-    for (int g = 0; g <= kGroups; ++g) {
-      if (g < kGroups) {
+    for (int g = 0; g < kGroups; ++g) {
+      double v[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int t = g * 8 + u;
-          if (t > 0) {
-            const int b = __builtin_ctz(t);
-            A = ((tile_state<TJ, ODD>(t) >> b) & 1u) ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
-          }
-          w[g & 1][u] = lds_f64(wt, A);
+      for (int u = 0; u < 4; ++u) {
+        const int t = g * 4 + u;
+        if (t > 0) {
+          const int b = __builtin_ctz(t);
+          A = ((tile_state<TJ, ODD>(t) >> b) & 1u) ? A + uint32_t(D[b]) : A - uint32_t(D[b]);
         }
+        v[u] = lds_f64(wt, A);
       }
-      if (g > 0) {
-        const int gp = g - 1;
-        const double(&v)[8] = w[gp & 1];
-        if (gp > 0) {   // a tile bit >= 3 flipped on entering this group
-          const int b = __builtin_ctz(gp * 8);
-          if ((tile_state<TJ, ODD>(gp * 8) >> b) & 1u)
-            U[b] -= sw;
-          else
-            U[b] += sw;
-        }
-        const double P01 = v[0] + v[1], P23 = v[2] + v[3], P45 = v[4] + v[5], P67 = v[6] + v[7];
-        const double Q0 = P01 + P23, Q1 = P45 + P67, G = Q0 + Q1;
+      if (g > 0) {   // a tile bit >= 2 flipped on entering this group
+        const int b = __builtin_ctz(g * 4);
+        if ((tile_state<TJ, ODD>(g * 4) >> b) & 1u)
+          U[b] -= sw;
+        else
+          U[b] += sw;
+      }
+      const double P01 = v[0] + v[1], P23 = v[2] + v[3], G = P01 + P23;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) U[b] += group_bit_sum<TJ, ODD>(gp, b, v, P23, P45, Q0, Q1, G);
-        sw += G;
-      }
+      for (int b = 0; b < 2; ++b) U[b] += group_bit_sum<TJ, ODD>(g, b, v, P01, P23, G);
+      sw += G;
     }
 #pragma unroll
-    for (int i = 3; i < TJ; ++i)
+    for (int i = 2; i < TJ; ++i)
       if ((kEnd >> i) & 1u) U[i] += sw;
   } else {
     // one or two tile bits: the prefix-sum trick per configuration
@@ -166,17 +151,18 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
   }
 }
 
-// Running totals of one lane over all the configurations it has walked.
+// Running sums of one thread over all the configurations it has walked.
 template <int TJ>
 struct LaneSums {
   double S;                 // W
   double Yt[TJ];            // W s_t, tile spins
   double Ym[kBwMid];        // W s_m, middle spins
   double Q[kBwMid][TJ];     // W s_m s_t
-  double M2[6];             // W s_m1 s_m2, pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+  double M2;                // W s_m0 s_m1
 
   __device__ __forceinline__ void clear() {
     S = 0.0;
+    M2 = 0.0;
 #pragma unroll
     for (int i = 0; i < TJ; ++i) Yt[i] = 0.0;
 #pragma unroll
@@ -185,21 +171,38 @@ struct LaneSums {
 #pragma unroll
       for (int i = 0; i < TJ; ++i) Q[m][i] = 0.0;
     }
-#pragma unroll
-    for (int j = 0; j < 6; ++j) M2[j] = 0.0;
   }
 
-  // W s_a for inner bit a (tile, then middle)
+  // W s_a for inner bit a (tile, then middle); a is a compile-time index
   __device__ __forceinline__ double inner(int a) const { return a < TJ ? Yt[a < TJ ? a : 0] : Ym[a < TJ ? 0 : a - TJ]; }
 };
 
+// Flip bit b (>= TJ) of state x (its own value in x does not matter: the
+// masks exclude it): move A by the bit's delta and the tile deltas D_i by
+// the plan constants kbit.  b is wave-uniform, so the plan constants come in
+// by scalar loads (flips happen between tile blocks, where waiting for them
+// costs nothing) and hold no vector registers during the walk.
 template <int TJ, int NC>
-__device__ inline void bond_chunk(const SiteTable<NC> &st, uint64_t x0, uint32_t rep_bytes, const char *wt,
-                                  LaneSums<TJ> &cs) {
-  uint32_t A;
-  int32_t D[TJ];
-  chunk_start<TJ, NC>(st, x0, rep_bytes, A, D);
-  const uint32_t nblk = 1u << (st.k - TJ);
+__device__ __forceinline__ void flip_bit(const DevPlan *__restrict__ P, const BondTables *__restrict__ T,
+                                         uint64_t x, int b, bool up, uint32_t &A, int32_t (&D)[TJ]) {
+  int32_t dm = P->up_base[b];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) dm -= P->cls_step[c] * int32_t(__popcll(x & P->mask[b][c]));
+  A = up ? A + uint32_t(dm) : A - uint32_t(dm);
+#pragma unroll
+  for (int i = 0; i < TJ; ++i) {
+    const int32_t kv = T->kbit[b][i];
+    D[i] = up ? D[i] + kv : D[i] - kv;
+  }
+}
+
+// All 2^k configurations of the chunk whose prefix is x0 (inner bits zero on
+// entry, with A and D those of x0).  On return the inner state is bit k - 1
+// alone (the reflected Gray code's last word), with A and D to match.
+template <int TJ, int NC>
+__device__ inline void bond_chunk(const DevPlan *__restrict__ P, const BondTables *__restrict__ T, uint64_t x0,
+                                  int mj, const char *wt, uint32_t &A, int32_t (&D)[TJ], LaneSums<TJ> &cs) {
+  const uint32_t nblk = 1u << mj;
   for (uint32_t q = 0; q < nblk; ++q) {
     double sw, U[TJ];
     if (q & 1)
@@ -222,12 +225,16 @@ __device__ inline void bond_chunk(const SiteTable<NC> &st, uint64_t x0, uint32_t
     }
 #pragma unroll
     for (int m = 0; m < kBwMid; ++m) cs.Ym[m] = fma(sg[m], sw, cs.Ym[m]);
-    int j = 0;
-#pragma unroll
-    for (int m1 = 0; m1 < kBwMid; ++m1)
-#pragma unroll
-      for (int m2 = m1 + 1; m2 < kBwMid; ++m2, ++j) cs.M2[j] = fma(sg[m1] * sg[m2], sw, cs.M2[j]);
-    if (q + 1 < nblk) middle_flip<TJ, NC>(st, x0, q, A, D);
+    cs.M2 = fma(sg[0] * sg[1], sw, cs.M2);
+    if (q + 1 < nblk) {
+      // Gray step q -> q + 1 of the middle bits: flips bit TJ + ctz(q + 1);
+      // the tile is at its end state (top bit set after an even block)
+      const uint32_t q1 = q + 1;
+      const int mm = __builtin_ctz(q1);
+      const bool up = (((q1 ^ (q1 >> 1)) >> mm) & 1u) != 0;
+      const uint64_t x = x0 | ((q & 1) ? 0ull : (1ull << (TJ - 1))) | (uint64_t(mid) << TJ);
+      flip_bit<TJ, NC>(P, T, x, TJ + mm, up, A, D);
+    }
   }
 }
 
@@ -257,110 +264,113 @@ __device__ __forceinline__ double wave_total(double v) {
 
 // v s_b, and v s_a s_b, for the spins of bits a and b of state x
 __device__ __forceinline__ double signed_by(uint64_t x, int b, double v) { return ((x >> b) & 1u) ? v : -v; }
-__device__ __forceinline__ double signed_by2(uint64_t x, int a, int b, double v) {
-  return (((x >> a) ^ (x >> b)) & 1u) ? -v : v;
-}
 
-// After a task: pairs with a task bit b, whose sign is the same for the whole
-// block but changes from task to task.  The task's part of a lane sum is the
-// growth of its wave total since the previous task (prev[], per wave, kept by
-// lane 63, which holds the totals); it is added to the pair's accumulator with
-// the task's sign of b.  One wave reduction per inner bit with task-bit
-// partners, per lane-fixed bit with task-bit partners (of W s_a, s_a fixed per
-// lane), and one of W for the task-task pairs.
+// At a flip of hi bit j (bit p, new sign s_p): every pair (a, p) gets
+// -(s_p(new) - s_p(old)) = -2 s_p(new) times the wave's running sum of
+// W s_a (inner a) or of W s_a over the state x before the flip (other a).
 template <int TJ>
-__device__ inline void flush_task(const BondTables *__restrict__ T, const LaneSums<TJ> &cs, uint64_t x0,
-                                  double *acc, double *prev, bool last_lane) {
+__device__ inline void flush_flip(const BondTables *__restrict__ T, const LaneSums<TJ> &cs, uint64_t x, int j,
+                                  bool up, double *acc, bool last_lane) {
+  const double c = up ? -2.0 : 2.0;
 #pragma unroll
   for (int a = 0; a < TJ + kBwMid; ++a) {
-    const int e0 = T->it_start[a], e1 = T->it_start[a + 1];
-    if (e0 < e1) {
-      const double c = wave_total(cs.inner(a));
-      if (last_lane) {
-        const double r = c - prev[a];
-        prev[a] = c;
-        for (int e = e0; e < e1; ++e) acc[T->it_pair[e]] += signed_by(x0, T->it_bit[e], r);
-      }
+    const int pr = T->hp_inner[j][a];
+    if (pr >= 0) {
+      const double v = wave_total(cs.inner(a));
+      if (last_lane) acc[pr] += c * v;
     }
   }
-  const int n_ltg = T->n_ltg;
-  for (int g = 0; g < n_ltg; ++g) {
-    const double c = wave_total(signed_by(x0, T->ltg_a[g], cs.S));
-    if (last_lane) {
-      const double r = c - prev[kInner + g];
-      prev[kInner + g] = c;
-      const int e1 = T->ltg_start[g + 1];
-      for (int e = T->ltg_start[g]; e < e1; ++e) acc[T->lt_pair[e]] += signed_by(x0, T->lt_bit[e], r);
-    }
-  }
-  const int n_tt = T->n_tt;
-  if (n_tt > 0) {
-    const double c = wave_total(cs.S);
-    if (last_lane) {
-      const double r = c - prev[kInner + kLaneBits];
-      prev[kInner + kLaneBits] = c;
-      for (int e = 0; e < n_tt; ++e)
-        acc[T->tt_pair[e]] += signed_by2(x0, T->tt_a[e], T->tt_b[e], r);
-    }
+  const int e1 = T->hp_start[j + 1];
+  for (int e = T->hp_start[j]; e < e1; ++e) {
+    const double v = wave_total(signed_by(x, T->hp_a[e], cs.S));
+    if (last_lane) acc[T->hp_pair[e]] += c * v;
   }
 }
 
-// At the end: pairs whose sign pattern is fixed per lane (x: the lane's
-// lane-fixed bits in place, other prefix bits 0), one wave reduction each:
-// tile-middle and middle-middle pairs from Q and M2, inner a - lane-fixed b
-// from W s_a times s_b, lane-fixed pairs from W times s_a s_b.
+// Final reduction of per-lane values through LDS, one wave at a time: the
+// wave stores up to kRound values of its 64 lanes (value c of lane s at slot
+// 64 c + s), then lane 8 v + u adds value v of lanes 8 u .. 8 u + 7, reading
+// them in the rotated order 8 u + ((r + u + v) mod 8), r = 0..7, so that the
+// 32 lanes a cycle serves read 32 different banks; a DPP tree over the 8
+// lanes of a group (row_shr 1, 2, 4: a group never straddles a row of 16)
+// leaves value v's total in lane 8 v + 7, which adds it to the pair's
+// accumulator.  Only the wave's own slots are used, so wave-scope fences
+// order the writes and reads (no block barrier).
+struct EndRounds {
+  double *buf;     // this wave's kRound x 64 doubles
+  int *ids;        // this wave's kRound pair ids
+  double *acc;     // this wave's pair accumulators
+  int lane;
+  int cnt = 0;
+
+  __device__ void push(double v, int pair) {
+    buf[cnt * kWave + lane] = v;
+    if (lane == 0) ids[cnt] = pair;
+    if (++cnt == kRound) flush();
+  }
+
+  __device__ void flush() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int v = lane >> 3, u = lane & 7;
+    double s = 0.0;
+    if (v < cnt)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) s += buf[v * kWave + u * 8 + ((r + u + v) & 7)];
+    s += dpp_f64<0x111, 0xf, true>(s);   // row_shr:1
+    s += dpp_f64<0x112, 0xf, true>(s);   // row_shr:2
+    s += dpp_f64<0x114, 0xf, true>(s);   // row_shr:4
+    if (u == 7 && v < cnt) acc[ids[v]] += s;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    cnt = 0;
+  }
+};
+
+// At the end: every pair with a non-inner bit (its sign pattern for the
+// final state x of the thread) and the tile-middle and middle-middle pairs.
 template <int TJ>
 __device__ inline void flush_end(const BondTables *__restrict__ T, const LaneSums<TJ> &cs, uint64_t x,
-                                 double *acc, bool last_lane) {
+                                 EndRounds &R) {
 #pragma unroll
   for (int m = 0; m < kBwMid; ++m)
 #pragma unroll
     for (int i = 0; i < TJ; ++i) {
       const int p = T->qpair[m][i];
-      if (p >= 0) {
-        const double v = wave_total(cs.Q[m][i]);
-        if (last_lane) acc[p] += v;
-      }
+      if (p >= 0) R.push(cs.Q[m][i], p);
     }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int p = T->m2pair[j];
-    if (p >= 0) {
-      const double v = wave_total(cs.M2[j]);
-      if (last_lane) acc[p] += v;
-    }
-  }
+  if (T->m2pair >= 0) R.push(cs.M2, T->m2pair);
 #pragma unroll
   for (int a = 0; a < TJ + kBwMid; ++a) {
-    const int e1 = T->il_start[a + 1];
-    for (int e = T->il_start[a]; e < e1; ++e) {
-      const double v = wave_total(signed_by(x, T->il_bit[e], cs.inner(a)));
-      if (last_lane) acc[T->il_pair[e]] += v;
-    }
+    const int e1 = T->end_start[a + 1];
+    for (int e = T->end_start[a]; e < e1; ++e) R.push(signed_by(x, T->end_b[e], cs.inner(a)), T->end_pair[e]);
   }
-  const int n_ll = T->n_ll;
-  for (int e = 0; e < n_ll; ++e) {
-    const double v = wave_total(signed_by2(x, T->ll_a[e], T->ll_b[e], cs.S));
-    if (last_lane) acc[T->ll_pair[e]] += v;
-  }
+  const int n_eo = T->n_end_outer;
+  for (int e = 0; e < n_eo; ++e)
+    R.push(signed_by(x, T->eo_b[e], signed_by(x, T->eo_a[e], cs.S)), T->eo_pair[e]);
+  if (R.cnt > 0) R.flush();
 }
 
 template <int TJ, int NC>
 __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
     const DevPlan *__restrict__ P, const BondTables *__restrict__ T, const double *__restrict__ Wd,
-    uint64_t n_chunks, uint64_t t_begin, uint64_t n_tasks, int mirror, double *__restrict__ partial) {
-  // Tasks [t_begin, n_tasks).  With mirror set, the table holds
-  // W(E, M) + W(E, -M) (column n_up plus column N - n_up), for a walk over the
-  // half of the configurations whose top spin is up.
-  // Static LDS (compile-time base): the weight table at offset 0, then the
-  // per-wave pair accumulators.
+    int n_walk, uint64_t hi_init, int mirror, double *__restrict__ partial) {
+  // The hi bits walk 2^n_walk states in Gray order from hi_init (with mirror
+  // set, the top hi bit stays up and the table holds W(E, M) + W(E, -M):
+  // column n_up plus column N - n_up, for the half of the configurations
+  // whose top spin is up).
+  // Static LDS (compile-time base): the per-wave pair accumulators at offset
+  // 0, then the weight table; the final reduction reuses the table's space.
   __shared__ __align__(16) double lds[kHistBytes / 8];
+  const int n_pairs = T->n_pairs;
+  const int acc_bytes = T->acc_bytes;
   const char *wt = reinterpret_cast<const char *>(lds);
+  double *tbl = lds + acc_bytes / 8;
   const int rw = T->rw, Wc = P->W, n_m = P->n_m;
   const int bins = P->n_ec * Wc;
-  // Each bin's weight is read from global memory once (eight loads in flight
+  // Each bin's weight is read from global memory once (four loads in flight
   // per thread) and written to its rw copies.
-  constexpr int kFill = 8;
+  constexpr int kFill = 4;
   for (int base = 0; base < bins; base += kFill * int(blockDim.x)) {
     double v[kFill];
 #pragma unroll
@@ -375,38 +385,61 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
     for (int j = 0; j < kFill; ++j) {
       const int bin = base + j * int(blockDim.x) + int(threadIdx.x);
       if (bin < bins)
-        for (int c = 0; c < rw; ++c) lds[bin * rw + c] = v[j];
+        for (int c = 0; c < rw; ++c) tbl[bin * rw + c] = v[j];
     }
   }
-  const int n_pairs = T->n_pairs;
-  double *acc_all = lds + T->wt_bytes / 8;
-  double *prev_all = acc_all + kBwWaves * n_pairs;
-  for (int i = threadIdx.x; i < kBwWaves * (n_pairs + kPrevSlots); i += blockDim.x) acc_all[i] = 0.0;
+  for (int i = threadIdx.x; i < kBwWaves * n_pairs; i += blockDim.x) lds[i] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const bool last_lane = lane == kWave - 1;
-  double *acc = acc_all + wave * n_pairs;
-  double *prev = prev_all + wave * kPrevSlots;
-  SiteTable<NC> st;
-  st.load(P, lane);
-  const uint32_t rep_bytes = uint32_t(lane & (rw - 1)) * 8u;
-  // A block has kBwWaves * kWave = 2^kLaneBits threads, so a thread's chunks
-  // share their low kLaneBits bits (its offset).
+  double *acc = lds + wave * n_pairs;
+  const int k = P->inner, mj = T->mj;
+  const int hi0 = k + kLaneBits + T->s_bits;
   const uint32_t offset = T->lane_chunk[threadIdx.x];
+  const bool active = int(offset) < T->n_offsets;
+  // first configuration: the thread's offset, the block's index, the hi start
+  uint64_t x = (uint64_t(offset) << k) | (uint64_t(blockIdx.x) << (k + kLaneBits));
+  if (T->n_hi > 0) x |= hi_init << hi0;
+  const uint32_t extra = uint32_t(acc_bytes) + uint32_t(lane & (rw - 1)) * 8u;   // table base + copy
+  uint32_t A = 0;
+  int32_t D[TJ];
+#pragma unroll
+  for (int i = 0; i < TJ; ++i) D[i] = 0;
+  {
+    SiteTable<NC> st;   // only for the set-up: flips read the plan by scalar loads
+    st.load(P, lane);
+    if (active) chunk_start<TJ, NC>(st, x, extra, A, D);
+  }
   LaneSums<TJ> cs;
   cs.clear();
-  for (uint64_t t = t_begin + blockIdx.x; t < n_tasks; t += gridDim.x) {
-    const uint64_t chunk = (t << kLaneBits) + offset;
-    const uint64_t x0 = chunk << st.k;
-    if (chunk < n_chunks) bond_chunk<TJ, NC>(st, x0, rep_bytes, wt, cs);
-    flush_task<TJ>(T, cs, x0, acc, prev, last_lane);
+  const uint64_t steps = uint64_t(1) << n_walk;
+  for (uint64_t t = 0;; ++t) {
+    if (active) bond_chunk<TJ, NC>(P, T, x, mj, wt, A, D, cs);
+    if (t + 1 == steps) break;
+    const int j = __builtin_ctzll(t + 1), p = hi0 + j;
+    const bool up = ((x >> p) & 1u) == 0;
+    flush_flip<TJ>(T, cs, x, j, up, acc, last_lane);
+    if (active) {
+      // back to the chunk's start (bit k - 1 down), then flip hi bit p
+      if (mj > 0)
+        flip_bit<TJ, NC>(P, T, x | (uint64_t(1) << (k - 1)), k - 1, false, A, D);
+      else
+        A -= uint32_t(D[TJ - 1]);
+      flip_bit<TJ, NC>(P, T, x, p, up, A, D);
+    }
+    x ^= uint64_t(1) << p;
   }
-  flush_end<TJ>(T, cs, uint64_t(offset) << st.k, acc, last_lane);
+  // final pair terms through LDS rounds over the (now unused) weight table:
+  // per wave kRound x 64 values, then kRound pair ids
   __syncthreads();
-  for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
+  int *round_ids = reinterpret_cast<int *>(tbl + kBwWaves * kRound * kWave);
+  EndRounds R{tbl + size_t(wave) * kRound * kWave, round_ids + wave * kRound, acc, lane};
+  flush_end<TJ>(T, cs, x, R);
+  __syncthreads();
+  for (int pr = threadIdx.x; pr < n_pairs; pr += blockDim.x) {
     double s = 0.0;
-    for (int w = 0; w < kBwWaves; ++w) s += acc_all[w * n_pairs + p];
-    partial[size_t(blockIdx.x) * n_pairs + p] = s;
+    for (int w = 0; w < kBwWaves; ++w) s += lds[w * n_pairs + pr];
+    partial[size_t(blockIdx.x) * n_pairs + pr] = s;
   }
 }
 
@@ -486,24 +519,23 @@ void bond_plan_free(BondPlan *b) {
 }
 
 template <int TJ, int NC>
-static ising_status launch_bond(const DevPlan *dP, const BondTables *dT, const double *W, uint64_t n_chunks,
-                                uint64_t t_begin, uint64_t n_tasks, int mirror, int grid, double *partial,
-                                hipStream_t s) {
-  hipLaunchKernelGGL((k_bond_backward<TJ, NC>), dim3(grid), dim3(kBwWaves * kWave), 0, s, dP, dT, W, n_chunks,
-                     t_begin, n_tasks, mirror, partial);
+static ising_status launch_bond(const DevPlan *dP, const BondTables *dT, const double *W, int n_walk,
+                                uint64_t hi_init, int mirror, int grid, double *partial, hipStream_t s) {
+  hipLaunchKernelGGL((k_bond_backward<TJ, NC>), dim3(grid), dim3(kBwWaves * kWave), 0, s, dP, dT, W, n_walk,
+                     hi_init, mirror, partial);
   HIP_TRY(hipGetLastError());
   return ISING_OK;
 }
 
 static ising_status bond_dispatch(int tile, int n_classes, const DevPlan *dP, const BondTables *dT, const double *W,
-                                  uint64_t n_chunks, uint64_t t_begin, uint64_t n_tasks, int mirror, int grid,
-                                  double *partial, hipStream_t s) {
+                                  int n_walk, uint64_t hi_init, int mirror, int grid, double *partial,
+                                  hipStream_t s) {
 #define ISING_BW_NC(TJ)                                                                                   \
   switch (n_classes) {                                                                                    \
-    case 1: return launch_bond<TJ, 1>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
-    case 2: return launch_bond<TJ, 2>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
-    case 4: return launch_bond<TJ, 4>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
-    case 8: return launch_bond<TJ, 8>(dP, dT, W, n_chunks, t_begin, n_tasks, mirror, grid, partial, s);   \
+    case 1: return launch_bond<TJ, 1>(dP, dT, W, n_walk, hi_init, mirror, grid, partial, s);             \
+    case 2: return launch_bond<TJ, 2>(dP, dT, W, n_walk, hi_init, mirror, grid, partial, s);             \
+    case 4: return launch_bond<TJ, 4>(dP, dT, W, n_walk, hi_init, mirror, grid, partial, s);             \
+    case 8: return launch_bond<TJ, 8>(dP, dT, W, n_walk, hi_init, mirror, grid, partial, s);             \
   }                                                                                                       \
   break;
   switch (tile) {
@@ -520,13 +552,14 @@ static ising_status bond_dispatch(int tile, int n_classes, const DevPlan *dP, co
   return fail(ISING_EUNSUPPORTED, "tile bits or class count out of range");
 }
 
-// One backward launch: device tables, work range and grid.
+// One backward launch: device tables, the hi-bit walk and the grid.
 struct BondLaunch {
   const DevPlan *dP = nullptr;
   const BondTables *dT = nullptr;
   const int32_t *dmap = nullptr;
-  uint64_t n_chunks = 0, t_begin = 0, n_tasks = 0;
-  int grid = 0;
+  int n_walk = 0;          // hi bits walked in Gray order
+  uint64_t hi_init = 0;    // their first state
+  int grid = 0;            // 2^s_bits blocks
   bool mirror = false;
 };
 
@@ -541,26 +574,24 @@ static ising_status bond_setup(const ising_plan *pc, bool halve, bool may_alloca
   L->dP = reinterpret_cast<const DevPlan *>(tables);
   L->dT = reinterpret_cast<const BondTables *>(tables + sizeof(DevPlan));
   L->dmap = reinterpret_cast<const int32_t *>(tables + sizeof(DevPlan) + sizeof(BondTables));
-  int cus = 0;
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  L->n_chunks = uint64_t(1) << (bp->geo.n - bp->geo.inner);
-  static_assert(kBwWaves * kWave == 1 << kLaneBits, "a block walks 2^kLaneBits chunks per task");
-  const uint64_t block = uint64_t(kBwWaves) * kWave;
-  L->n_tasks = (L->n_chunks + block - 1) / block;
-  // Halving needs the top spin to be a task bit (at least two tasks, both
-  // powers of two): tasks [n_tasks/2, n_tasks) are the configurations with
-  // it up.  Smaller lattices take the full walk, with the same result.
-  L->mirror = halve && L->n_tasks >= 2;
-  L->t_begin = L->mirror ? L->n_tasks / 2 : 0;
-  L->grid = int(std::min<uint64_t>({L->n_tasks - L->t_begin, uint64_t(cus), uint64_t(kMaxBwBlocks)}));
+  static_assert(kBwWaves * kWave == 1 << kLaneBits, "a block has 2^kLaneBits threads, one chunk offset each");
+  const int n_hi = bp->tables.n_hi;
+  // Halving needs the top spin to be a hi bit: it stays up, the other hi
+  // bits are walked.  Lattices without hi bits take the full walk, with the
+  // same result.
+  L->mirror = halve && n_hi >= 1;
+  L->n_walk = L->mirror ? n_hi - 1 : n_hi;
+  L->hi_init = L->mirror ? uint64_t(1) << (n_hi - 1) : 0;
+  L->grid = 1 << bp->tables.s_bits;
+  if (L->grid > kMaxBwBlocks) return fail(ISING_EUNSUPPORTED, "internal: backward grid too large");
   return ISING_OK;
 }
 
 static ising_status bond_launch(const ising_plan *pc, const BondLaunch &L, const double *W_dev, double *partial,
                                 double *dJ_dev, hipStream_t s) {
   const BondPlan *bp = pc->bond;
-  ising_status st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, L.dP, L.dT, W_dev, L.n_chunks, L.t_begin,
-                                  L.n_tasks, L.mirror ? 1 : 0, L.grid, partial, s);
+  ising_status st = bond_dispatch(bp->geo.tile, bp->geo.n_classes, L.dP, L.dT, W_dev, L.n_walk, L.hi_init,
+                                  L.mirror ? 1 : 0, L.grid, partial, s);
   if (st != ISING_OK) return st;
   hipLaunchKernelGGL(k_bond_finish, dim3(unsigned(bp->tables.n_pairs)), dim3(kFinishThreads), 0, s, L.dT, L.dmap,
                      partial, L.grid, dJ_dev);
@@ -639,9 +670,118 @@ static ising_status bond_backward_noalloc(const ising_plan *pc, const double *W_
   return bond_launch(pc, L, W_dev, partial, dJ_dev, static_cast<hipStream_t>(stream));
 }
 
+// thermo.hip
+ising_status first_derivatives_launch(const uint64_t *g, int32_t n_e, int32_t n_m, int32_t e_min, int32_t n_spins,
+                                      const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
+                                      const double *logz, double *d_T, double *d_h, hipStream_t stream);
+ising_status grid_contract_launch(const double *G, const double *d_T, const double *d_h, int nT, int nh,
+                                  double *grad_T, double *grad_h, hipStream_t stream);
+
+__global__ void k_zero_f64(double *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+static ising_status zero_f64(double *p, int n, hipStream_t s) {
+  if (!p || n <= 0) return ISING_OK;
+  hipLaunchKernelGGL(k_zero_f64, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, p, n);
+  HIP_TRY(hipGetLastError());
+  return ISING_OK;
+}
+
+// Workspace layout of ising_logz_backward: d_T and d_h on the grid, the bin
+// weights, then the per-bond backward's partial sums, each 256-byte aligned.
+struct BackwardLayout {
+  size_t d_T = 0, d_h = 0, W = 0, bond = 0, total = 0;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static ising_status backward_layout(const ising_plan *p, int32_t nT, int32_t nh, bool want_th, bool want_J,
+                                    BackwardLayout *L) {
+  if (nT < 0 || nh < 0 || int64_t(nT) * nh > (int64_t(1) << 30)) return fail(ISING_EINVAL, "bad grid size");
+  const size_t pts = size_t(nT) * size_t(nh) * sizeof(double);
+  const size_t tbl = size_t(2 * p->S + 1) * size_t(p->n_spins + 1) * sizeof(double);
+  size_t at = 0;
+  if (want_th) {
+    L->d_T = at;
+    at += align256(pts);
+    L->d_h = at;
+    at += align256(pts);
+  }
+  if (want_J) {
+    size_t bw = 0;
+    ising_status st = ising_bond_workspace(p, &bw);
+    if (st != ISING_OK) return st;
+    L->W = at;
+    at += align256(tbl);
+    L->bond = at;
+    at += align256(bw);
+  }
+  L->total = std::max<size_t>(at, 256);
+  return ISING_OK;
+}
+
 }  // namespace ising
 
 using namespace ising;
+
+extern "C" ising_status ising_logz_backward_workspace(const ising_plan *p, int32_t nT, int32_t nh, size_t *bytes) {
+  if (!p || !bytes) return fail(ISING_EINVAL, "plan or bytes is NULL");
+  BackwardLayout L;
+  ising_status st = backward_layout(p, nT, nh, true, p->n_bonds > 0, &L);
+  if (st != ISING_OK) return st;
+  *bytes = L.total;
+  return ISING_OK;
+}
+
+extern "C" ising_status ising_logz_backward(const ising_plan *p, const uint64_t *g_dev, const double *T_dev,
+                                            int32_t nT, const double *h_dev, int32_t nh, const double *logz_dev,
+                                            const double *G_dev, double *grad_T, double *grad_h, double *grad_J,
+                                            int32_t symmetric, void *workspace, size_t workspace_bytes,
+                                            void *stream) {
+  if (!p || !g_dev) return fail(ISING_EINVAL, "plan or g_dev is NULL");
+  const bool want_th = grad_T || grad_h;
+  const bool want_J = grad_J && p->n_bonds > 0;
+  if (!want_th && !want_J) return ISING_OK;
+  if (nT < 0 || nh < 0) return fail(ISING_EINVAL, "negative grid size");
+  if (nT == 0 || nh == 0) {   // an empty grid: every gradient is zero (a fill kernel, no memset node)
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ising_status st = zero_f64(grad_T, nT, s);
+    if (st == ISING_OK) st = zero_f64(grad_h, nh, s);
+    if (st == ISING_OK && want_J) st = zero_f64(grad_J, p->n_bonds, s);
+    return st;
+  }
+  if (!T_dev || !h_dev || !logz_dev || !G_dev || !workspace)
+    return fail(ISING_EINVAL, "T_dev, h_dev, logz_dev, G_dev or workspace is NULL");
+  BackwardLayout L;
+  ising_status st = backward_layout(p, nT, nh, want_th, want_J, &L);
+  if (st != ISING_OK) return st;
+  if (workspace_bytes < L.total)
+    return fail(ISING_EINVAL, "workspace of " + std::to_string(workspace_bytes) + " bytes; " +
+                                  std::to_string(L.total) + " needed");
+  char *ws = static_cast<char *>(workspace);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t n_e = int32_t(2 * p->S + 1), n_m = p->n_spins + 1, e_min = int32_t(-p->S);
+  if (want_th) {
+    double *dT = reinterpret_cast<double *>(ws + L.d_T), *dh = reinterpret_cast<double *>(ws + L.d_h);
+    st = first_derivatives_launch(g_dev, n_e, n_m, e_min, p->n_spins, T_dev, nT, h_dev, nh, logz_dev, dT, dh, s);
+    if (st != ISING_OK) return st;
+    st = grid_contract_launch(G_dev, dT, dh, nT, nh, grad_T, grad_h, s);
+    if (st != ISING_OK) return st;
+  }
+  if (want_J) {
+    double *W = reinterpret_cast<double *>(ws + L.W);
+    st = ising_bin_weights(g_dev, n_e, n_m, e_min, p->n_spins, T_dev, nT, h_dev, nh, logz_dev, G_dev, W, stream);
+    if (st != ISING_OK) return st;
+    size_t bw = 0;
+    st = ising_bond_workspace(p, &bw);
+    if (st != ISING_OK) return st;
+    st = bond_backward(p, W, grad_J, ws + L.bond, bw, symmetric != 0, stream);
+    if (st != ISING_OK) return st;
+  }
+  return ISING_OK;
+}
 
 extern "C" ising_status ising_bond_backward(const ising_plan *pc, const double *W_dev, double *dJ_dev,
                                             void *workspace, size_t workspace_bytes, void *stream) {

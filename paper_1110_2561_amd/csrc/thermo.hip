@@ -128,28 +128,35 @@ struct StagedBins {
 };
 
 // Copy the nonzero bins of a dense table into LDS as (ln g, E, M), thread by
-// thread in a fixed order.  Returns their number, or -1 (every thread) when
-// more than kStageBins.  scan: blockDim.x + 1 ints of LDS.
+// thread in a fixed order (thread t takes the bins t, t + blockDim, ...; its
+// entries follow those of threads 0 .. t-1).  Returns their number, or -1
+// (every thread) when more than kStageBins.  scan: blockDim.x / 64 + 1 ints
+// of LDS for the per-wave totals.
 __device__ int stage_bins(const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
                           double *lg, int *E, int *M, int *scan) {
   const int bins = n_e * n_m;
   int mine = 0;
   for (int i = threadIdx.x; i < bins; i += blockDim.x) mine += g[i] != 0ull;
-  scan[threadIdx.x] = mine;
+  // exclusive prefix over the block: inclusive scan within the wave by
+  // shuffles, then the wave totals in order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) scan[wv] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int t = 0; t < int(blockDim.x); ++t) {
-      const int c = scan[t];
-      scan[t] = run;
-      run += c;
-    }
-    scan[blockDim.x] = run;
+  int before = 0, total = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int t = scan[w];
+    if (w < wv) before += t;
+    total += t;
   }
   __syncthreads();
-  const int total = scan[blockDim.x];
   if (total > kStageBins) return -1;
-  int at = scan[threadIdx.x];
+  int at = before + incl - mine;
   for (int i = threadIdx.x; i < bins; i += blockDim.x) {
     const unsigned long long v = g[i];
     if (!v) continue;
@@ -288,7 +295,7 @@ constexpr int kTPerBlock = 8;   // temperatures per block of the batched kernel
 struct StageLds {
   double lg[kStageBins];
   int E[kStageBins], M[kStageBins];
-  int scan[kThermoThreads + 1];
+  int scan[kThermoThreads / 64 + 1];
   double sh[(kThermoThreads / 64) * 3 * kHPerBlock];
 };
 
@@ -350,6 +357,85 @@ __global__ __launch_bounds__(256) void k_bin_weights(
   }
 }
 
+// First derivatives of log Z for the backward, with the log Z of the
+// forward as normaliser (one pass, no max pass): block (a, f) covers the
+// temperature T_a and fields 8 f .. 8 f + 7, two per wave; the table's
+// nonzero bins are staged in LDS; per field, with p = g exp(-(E - hM)/T -
+// log Z) over the bins: d_T = (sum p H / sum p) / T^2, d_h = (sum p M / sum p)
+// / T, the sums over a wave's lanes in a fixed shuffle tree.  Tables with
+// more nonzero bins than the stage holds are read in place.
+constexpr int kFirstFields = 8;
+
+template <class Bins>
+__device__ void first_points(const Bins &B, double T, const double *__restrict__ hg, const double *__restrict__ lz,
+                             int c0, int cnt, double *__restrict__ d_T, double *__restrict__ d_h, int pt0) {
+  const int lane = threadIdx.x & 63;
+  const int bins = B.count();
+  const double inv_T = (T > 0.0 && isfinite(T)) ? 1.0 / T : 0.0;
+  double hv[2], lzv[2], s0[2] = {0.0, 0.0}, sH[2] = {0.0, 0.0}, sM[2] = {0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    hv[j] = j < cnt ? hg[c0 + j] : 0.0;
+    lzv[j] = j < cnt ? lz[pt0 + j] : 0.0;
+  }
+  for (int i = lane; i < bins; i += 64) {
+    double lg, E, M;
+    if (!B.get(i, lg, E, M)) continue;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double H = E - hv[j] * M;
+      const double p = exp(lg - H * inv_T - lzv[j]);
+      s0[j] += p;
+      sH[j] += p * H;
+      sM[j] += p * M;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    s0[j] = wave_sum(s0[j]);
+    sH[j] = wave_sum(sH[j]);
+    sM[j] = wave_sum(sM[j]);
+  }
+  if (lane != 0) return;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (j >= cnt) break;
+    const bool ok = (T > 0.0) && isfinite(T) && isfinite(hv[j]) && isfinite(lzv[j]);
+    d_T[pt0 + j] = ok ? (sH[j] / s0[j]) * inv_T * inv_T : NAN;
+    d_h[pt0 + j] = ok ? (sM[j] / s0[j]) * inv_T : NAN;
+  }
+}
+
+__global__ __launch_bounds__(kThermoThreads) void k_first_derivatives(
+    const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
+    const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh, const double *__restrict__ logz,
+    double *__restrict__ d_T, double *__restrict__ d_h) {
+  __shared__ StageLds L;
+  const int a = blockIdx.x;
+  const int staged = stage_bins(g, n_e, n_m, e_min, n_spins, L.lg, L.E, L.M, L.scan);
+  const int c0 = blockIdx.y * kFirstFields + 2 * int(threadIdx.x / 64);
+  if (c0 >= nh) return;
+  const int cnt = min(2, nh - c0), pt0 = a * nh + c0;
+  if (staged >= 0)
+    first_points(StagedBins{L.lg, L.E, L.M, staged}, Tg[a], hg, logz, c0, cnt, d_T, d_h, pt0);
+  else
+    first_points(DenseBins{g, n_m, e_min, n_spins, n_e * n_m}, Tg[a], hg, logz, c0, cnt, d_T, d_h, pt0);
+}
+
+ising_status first_derivatives_launch(const uint64_t *g, int32_t n_e, int32_t n_m, int32_t e_min, int32_t n_spins,
+                                      const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
+                                      const double *logz, double *d_T, double *d_h, hipStream_t stream) {
+  if (nT == 0 || nh == 0) return ISING_OK;
+  const dim3 grid(unsigned(nT), unsigned((nh + kFirstFields - 1) / kFirstFields));
+  if (grid.y > 65535) return fail(ISING_EINVAL, "too many field values");
+  hipLaunchKernelGGL(k_first_derivatives, grid, dim3(kThermoThreads), 0, stream,
+                     reinterpret_cast<const unsigned long long *>(g), n_e, n_m, e_min, n_spins, T_dev, nT, h_dev,
+                     nh, logz, d_T, d_h);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_first_derivatives launch: ") + hipGetErrorString(e));
+  return ISING_OK;
+}
+
 // Batched: grid (ceil(nT / kTPerBlock), members); block (x, member) covers
 // kTPerBlock temperatures and every field; outputs [member][nT][nh].
 __global__ __launch_bounds__(kThermoThreads) void k_batch_thermo(
@@ -378,6 +464,41 @@ ising_status batch_thermo_launch(const BatchMember *meta_dev, int n_members, con
                      logz, mE, mM, C, chi);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_batch_thermo launch: ") + hipGetErrorString(e));
+  return ISING_OK;
+}
+
+// Contraction of per-point first derivatives with a loss gradient G over the
+// grid, for the backward of L = sum G log Z: wave a < nT writes
+// grad_T[a] = sum_c G[a][c] d_T[a][c], wave nT + c writes
+// grad_h[c] = sum_a G[a][c] d_h[a][c]; lane l adds the terms l, l + 64, ...
+// in order, then a fixed shuffle tree adds the lanes.
+__global__ __launch_bounds__(256) void k_grid_contract(const double *__restrict__ G, const double *__restrict__ d_T,
+                                                       const double *__restrict__ d_h, int nT, int nh,
+                                                       double *__restrict__ grad_T, double *__restrict__ grad_h) {
+  const int w = int(blockIdx.x * blockDim.x + threadIdx.x) / 64, lane = threadIdx.x & 63;
+  double s = 0.0;
+  if (w < nT) {
+    if (!grad_T) return;
+    for (int c = lane; c < nh; c += 64) s = fma(G[w * nh + c], d_T[w * nh + c], s);
+  } else if (w < nT + nh) {
+    if (!grad_h) return;
+    const int c = w - nT;
+    for (int a = lane; a < nT; a += 64) s = fma(G[a * nh + c], d_h[a * nh + c], s);
+  } else {
+    return;
+  }
+  s = wave_sum(s);
+  if (lane == 0) (w < nT ? grad_T[w] : grad_h[w - nT]) = s;
+}
+
+ising_status grid_contract_launch(const double *G, const double *d_T, const double *d_h, int nT, int nh,
+                                  double *grad_T, double *grad_h, hipStream_t stream) {
+  if (nT + nh == 0) return ISING_OK;
+  const int waves = nT + nh, blocks = (waves + 3) / 4;   // 4 waves per block
+  hipLaunchKernelGGL(k_grid_contract, dim3(unsigned(blocks)), dim3(256), 0, stream, G, d_T, d_h, nT, nh, grad_T,
+                     grad_h);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_grid_contract launch: ") + hipGetErrorString(e));
   return ISING_OK;
 }
 

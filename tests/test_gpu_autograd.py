@@ -116,13 +116,19 @@ def test_bond_backward_matches_oracle(api, name, symmetric):
 
 def _bond_kinds(plan, lat):
     """Where each bond's two spins sit in the backward walk: inner (tile and up
-    to 4 middle bits), lane (the next 9 bits, fixed per thread) or task (the
-    rest, fixed per block and task)."""
+    to 2 middle bits), offset (the next 10 bits, fixed per thread), block (up
+    to 8 bits, fixed per block) or hi (the rest, walked in Gray order)."""
     N, TJ = lat.n_spins, plan.tile_bits
-    kb = TJ + min(4, N - TJ)
+    above = max(0, N - TJ - 10)
+    s = min(8, above)
+    kb = TJ + min(2, above - s)
 
     def kind(bit):
-        return "inner" if bit < kb else ("lane" if bit < kb + 9 else "task")
+        if bit < kb:
+            return "inner"
+        if bit < kb + 10:
+            return "offset"
+        return "block" if bit < kb + 10 + s else "hi"
 
     out = {}
     for b, (i, j) in enumerate(zip(lat.bond_i, lat.bond_j)):
@@ -139,9 +145,9 @@ def _torus_bond(lat, b):
 
 @pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
 def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api, symmetric):
-    # The full 2^40 backward on the +-J 8x5 torus (about 2000 tasks per block),
-    # with a random weight table; two bonds of every kind of bit pair, each
-    # against the oracle's transfer-matrix split of that bond.
+    # The full 2^40 backward on the +-J 8x5 torus (12 hi bits: 4096 chunks per
+    # thread), with a random weight table; two bonds of every kind of bit pair,
+    # each against the oracle's transfer-matrix split of that bond.
     lat = L.workload("torus8x5_pm")["lattice"]
     Jh, Jv = L.torus_coupling_grids(lat)
     g = native.tm_torus(Jh, Jv)
@@ -150,7 +156,8 @@ def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api, symmetric
     plan = api.Plan(lat)
     kinds = _bond_kinds(plan, lat)
     print("8x5 bond kinds:", {k: len(v) for k, v in sorted(kinds.items())}, flush=True)
-    assert {"inner-task", "lane-task", "task-task", "inner-inner"} <= set(kinds)
+    assert {"inner-inner", "inner-offset", "inner-block", "inner-hi", "offset-offset", "offset-block",
+            "offset-hi", "block-block", "block-hi", "hi-hi"} <= set(kinds)
     dJ = api.bond_backward(plan, torch.from_numpy(W).cuda(), symmetric=symmetric).cpu().numpy()
     scale = (np.abs(W) * g.astype(np.float64)).sum()
     for k in sorted(kinds):
@@ -182,14 +189,15 @@ def test_torus6x6_backward_random_weights_equal_on_every_bond(api, symmetric):
 
 
 @pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
-@pytest.mark.parametrize("n,mid", [(21, 1), (23, 3), (25, 4), (19, 0), (12, 0)])
+@pytest.mark.parametrize("n,mid", [(22, 1), (23, 2), (26, 2), (19, 0), (12, 0)])
 def test_bond_backward_middle_widths(api, n, mid, symmetric):
-    # With a 3-bit tile the backward takes mid = min(4, n - 3 - 17) middle bits
-    # (fewer on small lattices, to keep 256 tasks), so these sizes cover every
-    # middle width, and with it every split of the spins between middle,
-    # thread-fixed and task bits.
+    # With a 3-bit tile the backward takes s = min(8, n - 13) block bits and
+    # mid = min(2, n - 13 - s) middle bits (fewer on small lattices, to keep
+    # 256 blocks); 26 spins leave 3 hi bits.  These sizes cover every middle
+    # width, and with it every split of the spins between middle, offset,
+    # block and hi bits.
     lat = L.random_bond_lattice(n, 3 * n, 100 + n, values=(-1, 1))
-    assert mid == max(0, min(4, n - 3 - 17))
+    assert mid == max(0, min(2, n - 13 - min(8, max(0, n - 13))))
     g, gp = native.bond_split(lat.n_spins, lat.bond_i, lat.bond_j, lat.bond_J)
     rng = np.random.default_rng(n)
     W = np.where(g > 0, rng.standard_normal(g.shape), 0.0)
@@ -391,3 +399,37 @@ def test_symmetric_backward_option_matches_full(ag):
         (gJ,) = torch.autograd.grad((f(T, h, J) * G).sum(), J)
         out.append(gJ.cpu().numpy())
     np.testing.assert_allclose(out[1], out[0], rtol=1e-12, atol=1e-13 * np.abs(out[0]).max())
+
+
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
+def test_logz_backward_one_call_matches_separate_kernels(api, symmetric):
+    # ising_logz_backward issues the derivative, weight and per-bond kernels in
+    # one call: its grad_J equals bin_weights + bond_backward bit for bit, and
+    # grad_T, grad_h are the derivative kernel's d_T, d_h contracted with G
+    lat = L.square_torus(4, 6, L.pm_couplings(48, 9))
+    plan = api.Plan(lat)
+    g = api.enumerate_g(plan)
+    T = torch.tensor([0.7, 1.3, 2.2, 4.0], dtype=torch.float64, device="cuda")
+    h = torch.tensor([-0.5, 0.0, 0.3], dtype=torch.float64, device="cuda")
+    lz = api.log_z(g, plan.e_min, lat.n_spins, T, h)
+    G = torch.from_numpy(np.random.default_rng(11).standard_normal((4, 3))).cuda()
+    gT, gh, gJ = api.logz_backward(plan, g, T, h, lz, G, symmetric=symmetric)
+    W = api.bin_weights(g, plan.e_min, lat.n_spins, T, h, lz, G)
+    assert torch.equal(gJ, api.bond_backward(plan, W, symmetric=symmetric))
+    d = api.logz_derivatives(g, plan.e_min, lat.n_spins, T, h)
+    Gn, dT, dh = G.cpu().numpy(), d["d_T"].cpu().numpy(), d["d_h"].cpu().numpy()
+    # the one-call path normalises by the forward's log Z in one pass, the
+    # derivative kernel by the largest term in two: equal up to rounding of
+    # the terms, |H| <= S + |h| N and |M| <= N
+    Tn, hn, S, N = T.cpu().numpy()[:, None], h.cpu().numpy()[None, :], lat.abs_coupling_sum, lat.n_spins
+    scT, sch = (S + np.abs(hn) * N) / Tn ** 2, N / Tn + 0 * hn
+    assert (np.abs(gT.cpu().numpy() - (Gn * dT).sum(1)) <= 1e-13 * (np.abs(Gn) * scT).sum(1)).all()
+    assert (np.abs(gh.cpu().numpy() - (Gn * dh).sum(0)) <= 1e-13 * (np.abs(Gn) * sch).sum(0)).all()
+    # parts may be skipped; an empty grid gives zero gradients
+    a, b, c = api.logz_backward(plan, g, T, h, lz, G, want=(False, True, False))
+    assert a is None and c is None and torch.equal(b, gh)
+    e0 = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    zT, zh, zJ = api.logz_backward(plan, g, T[:0], h, e0, e0)
+    assert zT.numel() == 0 and torch.equal(zh, torch.zeros_like(zh)) and torch.equal(zJ, torch.zeros_like(zJ))
+    with pytest.raises(ValueError):
+        api.logz_backward(plan, g, T, h, lz[:, :2], G)
