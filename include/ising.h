@@ -218,8 +218,13 @@ ising_status ising_bond_backward_symmetric(const ising_plan *plan, const double 
  *   (the averages in one pass over the bins with the given log Z as
  *   normaliser, <H> = sum p H / sum p, p = g exp(-(E - hM)/T - log Z); then
  *   contracted with G, each sum in index order),
- *   grad_J[k] = the ising_bond_backward sum of bond k with W = ising_bin_weights(G)
- *   (its halved form ising_bond_backward_symmetric when `symmetric` is nonzero).
+ *   grad_J[k] = the ising_bond_backward sum of bond k with the weights of
+ *   ising_bin_weights(G) (its halved form ising_bond_backward_symmetric when
+ *   `symmetric` is nonzero); the weights are formed from the factorisation
+ *   exp(-(E - hM)/T - log Z) = exp(-(E - E0)/T) exp((hM - E0)/T - log Z),
+ *   E0 = -S the table's lowest energy, the sum over fields taken per (T, n_up)
+ *   (each term summed directly where the split could leave the double range),
+ *   so they equal ising_bin_weights' up to rounding.
  * T_dev[nT], h_dev[nh], logz_dev and G_dev [nT][nh] are FP64 device arrays
  * (logz as ising_logz returns it for the same table and grid).  Outputs are
  * FP64 device arrays of nT, nh and n_bonds entries; any may be NULL, and that

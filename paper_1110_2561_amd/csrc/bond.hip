@@ -676,6 +676,11 @@ ising_status first_derivatives_launch(const uint64_t *g, int32_t n_e, int32_t n_
                                       const double *logz, double *d_T, double *d_h, hipStream_t stream);
 ising_status grid_contract_launch(const double *G, const double *d_T, const double *d_h, int nT, int nh,
                                   double *grad_T, double *grad_h, hipStream_t stream);
+ising_status bin_weights_launch(const uint64_t *g, int32_t n_e, int32_t n_m, int32_t e_min, int32_t n_spins,
+                                const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
+                                const double *logz, const double *G, double *W, double *scratch,
+                                hipStream_t stream);
+size_t bin_weights_scratch_bytes(int32_t nT, int32_t n_m);
 
 __global__ void k_zero_f64(double *p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -692,7 +697,7 @@ static ising_status zero_f64(double *p, int n, hipStream_t s) {
 // Workspace layout of ising_logz_backward: d_T and d_h on the grid, the bin
 // weights, then the per-bond backward's partial sums, each 256-byte aligned.
 struct BackwardLayout {
-  size_t d_T = 0, d_h = 0, W = 0, bond = 0, total = 0;
+  size_t d_T = 0, d_h = 0, W = 0, wscratch = 0, bond = 0, total = 0;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -715,6 +720,8 @@ static ising_status backward_layout(const ising_plan *p, int32_t nT, int32_t nh,
     if (st != ISING_OK) return st;
     L->W = at;
     at += align256(tbl);
+    L->wscratch = at;
+    at += align256(bin_weights_scratch_bytes(nT, p->n_spins + 1));
     L->bond = at;
     at += align256(bw);
   }
@@ -772,7 +779,8 @@ extern "C" ising_status ising_logz_backward(const ising_plan *p, const uint64_t 
   }
   if (want_J) {
     double *W = reinterpret_cast<double *>(ws + L.W);
-    st = ising_bin_weights(g_dev, n_e, n_m, e_min, p->n_spins, T_dev, nT, h_dev, nh, logz_dev, G_dev, W, stream);
+    st = bin_weights_launch(g_dev, n_e, n_m, e_min, p->n_spins, T_dev, nT, h_dev, nh, logz_dev, G_dev, W,
+                            reinterpret_cast<double *>(ws + L.wscratch), s);
     if (st != ISING_OK) return st;
     size_t bw = 0;
     st = ising_bond_workspace(p, &bw);

@@ -357,6 +357,103 @@ __global__ __launch_bounds__(256) void k_bin_weights(
   }
 }
 
+// The bin weights of the backward, from the factorisation of each term of
+//   W(E, M) = sum_a (1/T_a) sum_c G[a][c] exp(-(E - h_c M)/T_a - logz[a][c])
+// as exp(-(E - E0)/T_a) * exp((h_c M - E0)/T_a - logz[a][c]) with E0 = e_min
+// (the table's lowest energy, so the first factor is at most 1):
+// k_weight_factors forms, per temperature a and column n_up,
+// R[a][n_up] = sum_c G[a][c] exp((h_c M - E0)/T_a - logz[a][c]) and the largest
+// of those exponents X[a][n_up]; k_weight_combine adds, per nonzero bin,
+// exp(-(E - E0)/T_a) R[a][n_up] / T_a over a.  Each term is the same number as
+// in the direct sum; where splitting its exponent could leave the double
+// range (X > 600, or the energy factor below e^-600 while the product may not
+// be), that (bin, a) is summed directly over c.  One wave per output, lanes
+// over the summed index, fixed shuffle trees: every sum has a fixed order.
+__global__ __launch_bounds__(256) void k_weight_factors(
+    int n_m, int e_min, int n_spins, const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
+    const double *__restrict__ logz, const double *__restrict__ G, double *__restrict__ R,
+    double *__restrict__ X) {
+  const int lane = threadIdx.x & 63;
+  const int w = int(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+  if (w >= nT * n_m) return;
+  const int a = w / n_m, nu = w - a * n_m;
+  const double E0 = double(e_min);
+  const double inv_T = 1.0 / Tg[a], M = double(2 * nu - n_spins);
+  double r = 0.0, xm = -INFINITY;
+  for (int c = lane; c < nh; c += 64) {
+    const double x = (hg[c] * M - E0) * inv_T - logz[a * nh + c];
+    xm = fmax(xm, x);
+    const double gc = G[a * nh + c];
+    if (gc != 0.0) r = fma(gc, exp(x), r);
+  }
+  r = wave_sum(r);
+  xm = wave_max(xm);
+  if (lane == 0) {
+    R[w] = r;
+    X[w] = xm;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_weight_combine(
+    const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
+    const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
+    const double *__restrict__ logz, const double *__restrict__ G, const double *__restrict__ R,
+    const double *__restrict__ X, double *__restrict__ W) {
+  const int lane = threadIdx.x & 63;
+  const int waves = int(gridDim.x * (blockDim.x / 64));
+  for (int i = int(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64); i < n_e * n_m; i += waves) {
+    if (!g[i]) {   // uniform over the wave
+      if (lane == 0) W[i] = 0.0;
+      continue;
+    }
+    const int e = i / n_m, nu = i - e * n_m;
+    const double E = double(e + e_min), M = double(2 * nu - n_spins);
+    const double E0 = double(e_min);
+    double acc = 0.0;
+    for (int a = lane; a < nT; a += 64) {
+      const double inv_T = 1.0 / Tg[a];
+      const double x1 = -(E - E0) * inv_T;        // <= 0
+      const double xm = X[a * n_m + nu];           // largest second exponent of (a, n_up)
+      double term;
+      if (xm <= 600.0 && (x1 >= -600.0 || x1 + xm < -700.0)) {
+        term = exp(x1) * R[a * n_m + nu];
+      } else {   // direct: the exponent in one piece
+        term = 0.0;
+        for (int c = 0; c < nh; ++c) {
+          const double gc = G[a * nh + c];
+          if (gc != 0.0) term = fma(gc, exp(-(E - hg[c] * M) * inv_T - logz[a * nh + c]), term);
+        }
+      }
+      acc = fma(term, inv_T, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) W[i] = acc;
+  }
+}
+
+ising_status bin_weights_launch(const uint64_t *g, int32_t n_e, int32_t n_m, int32_t e_min, int32_t n_spins,
+                                const double *T_dev, int32_t nT, const double *h_dev, int32_t nh,
+                                const double *logz, const double *G, double *W, double *scratch,
+                                hipStream_t stream) {
+  // scratch: nT * n_m doubles (R), then nT * n_m doubles (X)
+  double *R = scratch, *X = scratch + size_t(nT) * n_m;
+  const int waves = nT * n_m;
+  hipLaunchKernelGGL(k_weight_factors, dim3(unsigned((waves + 3) / 4)), dim3(256), 0, stream, n_m, e_min, n_spins,
+                     T_dev, nT, h_dev, nh, logz, G, R, X);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_weight_factors launch: ") + hipGetErrorString(e));
+  const int bins = n_e * n_m;
+  const int blocks = std::min((bins + 3) / 4, 65536);   // four waves per block, one bin each
+  hipLaunchKernelGGL(k_weight_combine, dim3(unsigned(blocks)), dim3(256), 0, stream,
+                     reinterpret_cast<const unsigned long long *>(g), n_e, n_m, e_min, n_spins, T_dev, nT, h_dev,
+                     nh, logz, G, R, X, W);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(ISING_EHIP, std::string("k_weight_combine launch: ") + hipGetErrorString(e));
+  return ISING_OK;
+}
+
+size_t bin_weights_scratch_bytes(int32_t nT, int32_t n_m) { return size_t(2) * nT * n_m * sizeof(double); }
+
 // First derivatives of log Z for the backward, with the log Z of the
 // forward as normaliser (one pass, no max pass): block (a, f) covers the
 // temperature T_a and fields 8 f .. 8 f + 7, two per wave; the table's
