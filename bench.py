@@ -295,7 +295,9 @@ def bench_other_lattice(name: str, reps: int) -> dict:
 
 def bench_autograd(plain_rate: float, reps: int) -> dict:
     """log Z(T, h, J) on the 64 x 64 grid with its hand-written backward
-    (dT, dh from g; per-bond dJ by recomputed enumeration)."""
+    (dT, dh from g; per-bond dJ by recomputed enumeration): the time of
+    torch.autograd.grad through the autograd Function, and of the library's
+    one-call backward (ising_logz_backward) that the Function issues."""
     import torch
 
     from paper_1110_2561_amd import api
@@ -304,6 +306,10 @@ def bench_autograd(plain_rate: float, reps: int) -> dict:
     w = L.workload("autograd")
     out = {"grid": [len(w["T"]), len(w["h"])], "dtype": "f64 sums over u32/u64 enumeration",
            "backward": "dT, dh from g; per-bond dJ by a recomputed walk over all 2^N configurations",
+           "backward_ms": "torch.autograd.grad(sum log Z, (T, h, J)) through the autograd Function, "
+                          "with PyTorch's engine overhead",
+           "library_backward_ms": "the same gradients from one ising_logz_backward call (all its kernels on "
+                                  "one stream, no host synchronisation)",
            "backward_symmetric": "the same, dJ walking the half with the top spin up with weights "
                                  "W(E,M) + W(E,-M) (spin-flip symmetry); checked equal to the full form",
            "lattices": []}
@@ -330,6 +336,16 @@ def bench_autograd(plain_rate: float, reps: int) -> dict:
         assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(rhs)), (lhs, rhs)
         fms = _median_ms(fwd, reps)
         bms = _median_ms(bwd, reps)
+        lz, G = res["lz"].detach(), torch.ones_like(res["lz"])
+        Td, hd = T.detach(), h.detach()
+
+        def lib():
+            res["lib"] = api.logz_backward(f.plan, f.g, Td, hd, lz, G)
+
+        lib()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(res["lib"], res["g"])), "library backward differs"
+        lms = _median_ms(lib, reps)
         f.symmetric_backward = True          # the per-bond sums over half the configurations
         g_full = res["g"]
         bwd()
@@ -344,9 +360,10 @@ def bench_autograd(plain_rate: float, reps: int) -> dict:
                        + ("J=1)" if set(int(v) for v in lat.bond_J) == {1} else f"seeded +-J, seed {lat.seed})"),
             "forward_ms": fms,
             "backward_ms": bms,
-            "backward_value": configs / (bms * 1e-3),
+            "library_backward_ms": lms,
+            "backward_value": configs / (lms * 1e-3),
             "unit": "configs/s",
-            "vs_plain": configs / (bms * 1e-3) / plain_rate,
+            "vs_plain": configs / (lms * 1e-3) / plain_rate,
             "backward_symmetric_ms": sms,
             "backward_symmetric_covered": configs / (sms * 1e-3),
             "symmetric_vs_plain": configs / (sms * 1e-3) / plain_rate,
@@ -365,6 +382,8 @@ def main() -> int:
     ap.add_argument("--tile-bits", type=int, default=0, help="plan tile width (0 = the plan's choice)")
     ap.add_argument("--inner-bits", type=int, default=0, help="plan chunk width (0 = the plan's choice)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and autograd measurements")
+    ap.add_argument("--only", choices=["halving", "batched", "autograd", "6x6"], default=None,
+                    help="of the measurements beside the headline, run only this one (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -494,10 +513,15 @@ def main() -> int:
     line["build"] = {"sources_sha256": sources_sha256(), "arch": torch.cuda.get_device_properties(0).gcnArchName,
                      "cus": torch.cuda.get_device_properties(0).multi_processor_count}
     if not args.no_extras:
-        line["z2_halving"] = bench_symmetric(plan, g, configs, achieved, reps=5)
-        line["batched"] = bench_batched(achieved, reps=5)
-        line["autograd"] = bench_autograd(achieved, reps=5)
-        if args.workload != "torus6x6":
+        def want(name):
+            return args.only is None or args.only == name
+        if want("halving"):
+            line["z2_halving"] = bench_symmetric(plan, g, configs, achieved, reps=5)
+        if want("batched"):
+            line["batched"] = bench_batched(achieved, reps=5)
+        if want("autograd"):
+            line["autograd"] = bench_autograd(achieved, reps=5)
+        if want("6x6") and args.workload != "torus6x6":
             line["enumeration_6x6"] = bench_other_lattice("torus6x6", reps=10)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(lat, args.cpu_sample_log2)
