@@ -98,10 +98,10 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
                                             double (&U)[TJ]) {
   constexpr int kN = 1 << TJ;
   constexpr uint32_t kEnd = tile_state<TJ, ODD>(kN - 1);
-#pragma unroll
-  for (int i = 0; i < TJ; ++i) U[i] = 0.0;
-  sw = 0.0;
   if constexpr (TJ >= 3) {
+    // Each sum starts as its first term (no add of 0.0, which IEEE rules
+    // keep as an instruction since -0.0 + 0.0 is +0.0): the group-0 sums, and
+    // for a bit >= 2 the running total at its first flip.
     constexpr int kGroups = kN / 4;
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
@@ -117,21 +117,28 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
       }
       if (g > 0) {   // a tile bit >= 2 flipped on entering this group
         const int b = __builtin_ctz(g * 4);
-        if ((tile_state<TJ, ODD>(g * 4) >> b) & 1u)
-          U[b] -= sw;
+        const bool up = ((tile_state<TJ, ODD>(g * 4) >> b) & 1u) != 0;
+        if (g == (1 << (b - 2)))
+          U[b] = up ? -sw : sw;
         else
-          U[b] += sw;
+          U[b] = up ? U[b] - sw : U[b] + sw;
       }
       const double P01 = v[0] + v[1], P23 = v[2] + v[3], G = P01 + P23;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) U[b] += group_bit_sum<TJ, ODD>(g, b, v, P01, P23, G);
-      sw += G;
+      for (int b = 0; b < 2; ++b) {
+        const double gs = group_bit_sum<TJ, ODD>(g, b, v, P01, P23, G);
+        U[b] = g == 0 ? gs : U[b] + gs;
+      }
+      sw = g == 0 ? G : sw + G;
     }
 #pragma unroll
     for (int i = 2; i < TJ; ++i)
       if ((kEnd >> i) & 1u) U[i] += sw;
   } else {
     // one or two tile bits: the prefix-sum trick per configuration
+#pragma unroll
+    for (int i = 0; i < TJ; ++i) U[i] = 0.0;
+    sw = 0.0;
 #pragma unroll
     for (int t = 0; t < kN; ++t) {
       if (t > 0) {
@@ -151,30 +158,37 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
   }
 }
 
-// Running sums of one thread over all the configurations it has walked.
+// Running sums of one thread over all the configurations it has walked.  The
+// tile sums are kept over the configurations with the tile spin up (what a
+// tile block yields), so folding a block costs one add each; with s_t = +1
+// there and -1 elsewhere, W s_t = 2 Yu - S and W s_m s_t = 2 Qu - Ym.
 template <int TJ>
 struct LaneSums {
   double S;                 // W
-  double Yt[TJ];            // W s_t, tile spins
+  double Yu[TJ];            // W [s_t up], tile spins
   double Ym[kBwMid];        // W s_m, middle spins
-  double Q[kBwMid][TJ];     // W s_m s_t
+  double Qu[kBwMid][TJ];    // W s_m [s_t up]
   double M2;                // W s_m0 s_m1
 
   __device__ __forceinline__ void clear() {
     S = 0.0;
     M2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < TJ; ++i) Yt[i] = 0.0;
+    for (int i = 0; i < TJ; ++i) Yu[i] = 0.0;
 #pragma unroll
     for (int m = 0; m < kBwMid; ++m) {
       Ym[m] = 0.0;
 #pragma unroll
-      for (int i = 0; i < TJ; ++i) Q[m][i] = 0.0;
+      for (int i = 0; i < TJ; ++i) Qu[m][i] = 0.0;
     }
   }
 
   // W s_a for inner bit a (tile, then middle); a is a compile-time index
-  __device__ __forceinline__ double inner(int a) const { return a < TJ ? Yt[a < TJ ? a : 0] : Ym[a < TJ ? 0 : a - TJ]; }
+  __device__ __forceinline__ double inner(int a) const {
+    return a < TJ ? fma(2.0, Yu[a < TJ ? a : 0], -S) : Ym[a < TJ ? 0 : a - TJ];
+  }
+  // W s_m s_t for middle bit m and tile bit i
+  __device__ __forceinline__ double tile_middle(int m, int i) const { return fma(2.0, Qu[m][i], -Ym[m]); }
 };
 
 // Flip bit b (>= TJ) of state x (its own value in x does not matter: the
@@ -218,10 +232,9 @@ __device__ inline void bond_chunk(const DevPlan *__restrict__ P, const BondTable
     cs.S += sw;
 #pragma unroll
     for (int i = 0; i < TJ; ++i) {
-      const double y = 2.0 * U[i] - sw;
-      cs.Yt[i] += y;
+      cs.Yu[i] += U[i];
 #pragma unroll
-      for (int m = 0; m < kBwMid; ++m) cs.Q[m][i] = fma(sg[m], y, cs.Q[m][i]);
+      for (int m = 0; m < kBwMid; ++m) cs.Qu[m][i] = fma(sg[m], U[i], cs.Qu[m][i]);
     }
 #pragma unroll
     for (int m = 0; m < kBwMid; ++m) cs.Ym[m] = fma(sg[m], sw, cs.Ym[m]);
@@ -268,9 +281,12 @@ __device__ __forceinline__ double signed_by(uint64_t x, int b, double v) { retur
 // At a flip of hi bit j (bit p, new sign s_p): every pair (a, p) gets
 // -(s_p(new) - s_p(old)) = -2 s_p(new) times the wave's running sum of
 // W s_a (inner a) or of W s_a over the state x before the flip (other a).
+// Bits from `uniform` up (block and hi bits) are the same in every lane of
+// the block, so for such a the wave sum is s_a times the wave's sum of W,
+// taken once per flip.
 template <int TJ>
 __device__ inline void flush_flip(const BondTables *__restrict__ T, const LaneSums<TJ> &cs, uint64_t x, int j,
-                                  bool up, double *acc, bool last_lane) {
+                                  bool up, int uniform, double *acc, bool last_lane) {
   const double c = up ? -2.0 : 2.0;
 #pragma unroll
   for (int a = 0; a < TJ + kBwMid; ++a) {
@@ -281,8 +297,20 @@ __device__ inline void flush_flip(const BondTables *__restrict__ T, const LaneSu
     }
   }
   const int e1 = T->hp_start[j + 1];
+  bool have_total = false;
+  double total = 0.0;
   for (int e = T->hp_start[j]; e < e1; ++e) {
-    const double v = wave_total(signed_by(x, T->hp_a[e], cs.S));
+    const int a = T->hp_a[e];
+    double v;
+    if (a >= uniform) {
+      if (!have_total) {
+        total = wave_total(cs.S);
+        have_total = true;
+      }
+      v = signed_by(x, a, total);
+    } else {
+      v = wave_total(signed_by(x, a, cs.S));
+    }
     if (last_lane) acc[T->hp_pair[e]] += c * v;
   }
 }
@@ -337,7 +365,7 @@ __device__ inline void flush_end(const BondTables *__restrict__ T, const LaneSum
 #pragma unroll
     for (int i = 0; i < TJ; ++i) {
       const int p = T->qpair[m][i];
-      if (p >= 0) R.push(cs.Q[m][i], p);
+      if (p >= 0) R.push(cs.tile_middle(m, i), p);
     }
   if (T->m2pair >= 0) R.push(cs.M2, T->m2pair);
 #pragma unroll
@@ -418,7 +446,7 @@ __global__ __launch_bounds__(kBwWaves * kWave) void k_bond_backward(
     if (t + 1 == steps) break;
     const int j = __builtin_ctzll(t + 1), p = hi0 + j;
     const bool up = ((x >> p) & 1u) == 0;
-    flush_flip<TJ>(T, cs, x, j, up, acc, last_lane);
+    flush_flip<TJ>(T, cs, x, j, up, k + kLaneBits, acc, last_lane);
     if (active) {
       // back to the chunk's start (bit k - 1 down), then flip hi bit p
       if (mj > 0)
