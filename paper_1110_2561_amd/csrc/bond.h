@@ -31,8 +31,9 @@ constexpr int kRound = 8;           // values per wave in one LDS round of the f
 //   [k + L + s, N)       hi bits: every block walks all their states in Gray
 //                        order, one chunk per thread per state, so the next
 //                        chunk differs from the last in a single spin.
-// Each thread keeps running sums over all it has walked: W, W s_a for every
-// inner bit a, W s_t s_m (tile-middle) and W s_m1 s_m2 (middle-middle).  A
+// Each thread keeps running sums over all it has walked, from which W, W s_a
+// for every inner bit a, W s_t s_m (tile-middle) and W s_m1 s_m2
+// (middle-middle) follow.  A
 // pair whose sign pattern never changes for a thread (both bits inner,
 // offset or block bits) is read from them at the end.  A pair (a, p) with a
 // hi bit p takes, by summation by parts over the walk, s_p(end) times the

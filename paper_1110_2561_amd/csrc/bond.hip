@@ -24,7 +24,9 @@
 //     sequence, so a configuration costs one load, one integer add and two
 //     FP64 adds.
 //   * after each tile block the block's sums are folded into the thread's
-//     running sums: W, W s_a (every inner bit a), W s_t s_m, W s_m1 s_m2.
+//     running sums of W over the configurations with given inner spins up
+//     (none; tile spin t; middle spin m; m and t; both middle spins), from
+//     which W s_a, W s_t s_m and W s_m1 s_m2 follow when they are read.
 //   * pairs whose sign pattern is fixed for a thread are read from the
 //     running sums at the end; a pair with a hi bit p also gets, at every
 //     flip of p, -(change of s_p) times the running sums at that moment
@@ -158,37 +160,45 @@ __device__ __forceinline__ void weight_walk(uint32_t &A, const int32_t (&D)[TJ],
   }
 }
 
-// Running sums of one thread over all the configurations it has walked.  The
-// tile sums are kept over the configurations with the tile spin up (what a
-// tile block yields), so folding a block costs one add each; with s_t = +1
-// there and -1 elsewhere, W s_t = 2 Yu - S and W s_m s_t = 2 Qu - Ym.
+// Running sums of one thread over all the configurations it has walked,
+// kept over the configurations with given spins up (what a tile block yields,
+// and the middle spins are up for whole blocks), so folding a block costs one
+// add per sum it touches.  With s = 2 [s up] - 1, the signed sums follow when
+// they are read:
+//   W s_a        = 2 W[a] - W,
+//   W s_a s_b    = 4 W[a][b] - 2 W[a] - 2 W[b] + W,
+// where W[a] is the sum over the configurations with spin a up.
 template <int TJ>
 struct LaneSums {
   double S;                 // W
-  double Yu[TJ];            // W [s_t up], tile spins
-  double Ym[kBwMid];        // W s_m, middle spins
-  double Qu[kBwMid][TJ];    // W s_m [s_t up]
-  double M2;                // W s_m0 s_m1
+  double Yu[TJ];            // W [t up], tile spins
+  double Zm[kBwMid];        // W [m up], middle spins
+  double Qb[kBwMid][TJ];    // W [m up][t up]
+  double M2b;               // W [m0 up][m1 up]
 
   __device__ __forceinline__ void clear() {
     S = 0.0;
-    M2 = 0.0;
+    M2b = 0.0;
 #pragma unroll
     for (int i = 0; i < TJ; ++i) Yu[i] = 0.0;
 #pragma unroll
     for (int m = 0; m < kBwMid; ++m) {
-      Ym[m] = 0.0;
+      Zm[m] = 0.0;
 #pragma unroll
-      for (int i = 0; i < TJ; ++i) Qu[m][i] = 0.0;
+      for (int i = 0; i < TJ; ++i) Qb[m][i] = 0.0;
     }
   }
 
   // W s_a for inner bit a (tile, then middle); a is a compile-time index
   __device__ __forceinline__ double inner(int a) const {
-    return a < TJ ? fma(2.0, Yu[a < TJ ? a : 0], -S) : Ym[a < TJ ? 0 : a - TJ];
+    return fma(2.0, a < TJ ? Yu[a < TJ ? a : 0] : Zm[a < TJ ? 0 : a - TJ], -S);
   }
   // W s_m s_t for middle bit m and tile bit i
-  __device__ __forceinline__ double tile_middle(int m, int i) const { return fma(2.0, Qu[m][i], -Ym[m]); }
+  __device__ __forceinline__ double tile_middle(int m, int i) const {
+    return fma(4.0, Qb[m][i], fma(-2.0, Yu[i] + Zm[m], S));
+  }
+  // W s_m0 s_m1
+  __device__ __forceinline__ double middle_pair() const { return fma(4.0, M2b, fma(-2.0, Zm[0] + Zm[1], S)); }
 };
 
 // Flip bit b (>= TJ) of state x (its own value in x does not matter: the
@@ -223,22 +233,21 @@ __device__ inline void bond_chunk(const DevPlan *__restrict__ P, const BondTable
       weight_walk<TJ, true>(A, D, wt, sw, U);
     else
       weight_walk<TJ, false>(A, D, wt, sw, U);
-    // middle spins during block q: bits of gray(q) (unused slots read -1 and
-    // are never consulted)
+    // middle spins during block q: bits of gray(q) (slots beyond mj stay
+    // down and are never consulted); the block's sums go into the sums of
+    // the middle spins that are up
     const uint32_t mid = q ^ (q >> 1);
-    double sg[kBwMid];
-#pragma unroll
-    for (int m = 0; m < kBwMid; ++m) sg[m] = ((mid >> m) & 1u) ? 1.0 : -1.0;
     cs.S += sw;
 #pragma unroll
-    for (int i = 0; i < TJ; ++i) {
-      cs.Yu[i] += U[i];
+    for (int i = 0; i < TJ; ++i) cs.Yu[i] += U[i];
 #pragma unroll
-      for (int m = 0; m < kBwMid; ++m) cs.Qu[m][i] = fma(sg[m], U[i], cs.Qu[m][i]);
-    }
+    for (int m = 0; m < kBwMid; ++m)
+      if ((mid >> m) & 1u) {
+        cs.Zm[m] += sw;
 #pragma unroll
-    for (int m = 0; m < kBwMid; ++m) cs.Ym[m] = fma(sg[m], sw, cs.Ym[m]);
-    cs.M2 = fma(sg[0] * sg[1], sw, cs.M2);
+        for (int i = 0; i < TJ; ++i) cs.Qb[m][i] += U[i];
+      }
+    if (mid == 3u) cs.M2b += sw;
     if (q + 1 < nblk) {
       // Gray step q -> q + 1 of the middle bits: flips bit TJ + ctz(q + 1);
       // the tile is at its end state (top bit set after an even block)
@@ -367,7 +376,7 @@ __device__ inline void flush_end(const BondTables *__restrict__ T, const LaneSum
       const int p = T->qpair[m][i];
       if (p >= 0) R.push(cs.tile_middle(m, i), p);
     }
-  if (T->m2pair >= 0) R.push(cs.M2, T->m2pair);
+  if (T->m2pair >= 0) R.push(cs.middle_pair(), T->m2pair);
 #pragma unroll
   for (int a = 0; a < TJ + kBwMid; ++a) {
     const int e1 = T->end_start[a + 1];
