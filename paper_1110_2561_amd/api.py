@@ -246,7 +246,8 @@ def logz_backward(plan: Plan, g: torch.Tensor, T: torch.Tensor, h: torch.Tensor,
     one library call (ising_logz_backward); an entry is None where `want` is
     false.  T, h: 1-D float64 device tensors; logz, grad: [len(T), len(h)]
     float64 device tensors; g: the plan's table.  The workspace is kept on the
-    plan (stream-ordered reuse)."""
+    plan, one per device (stream-ordered reuse: calls that overlap in time on
+    different streams need plans of their own)."""
     _check_table(plan, g)
     dev = g.device
     Tt, ht = _grid(T, dev), _grid(h, dev)
@@ -255,14 +256,18 @@ def logz_backward(plan: Plan, g: torch.Tensor, T: torch.Tensor, h: torch.Tensor,
     G = grad if grad.is_contiguous() else grad.contiguous()
     if lz.dtype != torch.float64 or G.dtype != torch.float64 or lz.shape != (nT, nh) or G.shape != (nT, nh):
         raise ValueError(f"logz and grad must be float64 tensors of shape {(nT, nh)}")
-    cache = plan.__dict__.setdefault("_lb", {})
-    key = (dev, nT, nh)
-    ws = cache.get(key)
-    if ws is None:
+    # one workspace per device, grown to the largest grid seen (the size of
+    # each grid shape is asked for once)
+    sizes = plan.__dict__.setdefault("_lb_bytes", {})
+    need = sizes.get((nT, nh))
+    if need is None:
         n = ctypes.c_size_t()
         _lib.check(_lib.ising_logz_backward_workspace(plan.handle, nT, nh, ctypes.byref(n)))
-        ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
-        cache[key] = ws
+        need = sizes[(nT, nh)] = n.value
+    cache = plan.__dict__.setdefault("_lb", {})
+    ws = cache.get(dev)
+    if ws is None or ws.numel() < need:
+        ws = cache[dev] = torch.empty(max(need, 8), dtype=torch.uint8, device=dev)
     gT = torch.empty(nT, dtype=torch.float64, device=dev) if want[0] else None
     gh = torch.empty(nh, dtype=torch.float64, device=dev) if want[1] else None
     gJ = torch.empty(plan.lattice.n_bonds, dtype=torch.float64, device=dev) if want[2] else None
