@@ -99,6 +99,7 @@ constexpr int kStageBins = 4096;  // nonzero bins a block keeps in LDS as (ln g,
 
 // Bins of a dense table, read in place: zero bins are skipped, ln g computed.
 struct DenseBins {
+  static constexpr bool kStaged = false;
   const unsigned long long *g;
   int n_m, e_min, n_spins, bins;
   __device__ int count() const { return bins; }
@@ -115,6 +116,7 @@ struct DenseBins {
 
 // Nonzero bins staged in LDS (stage_bins): every entry is a real bin.
 struct StagedBins {
+  static constexpr bool kStaged = true;
   const double *lg;
   const int *E, *M;
   int n;
@@ -205,21 +207,44 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
 #pragma unroll
   for (int j = cnt; j < P; ++j) m[j] = m[0];
 
-  // pass 2: Z' and first moments
+  // pass 2: Z' and first moments.  When the bins are staged and a full
+  // block holds at most KC per thread (bins i = t, t + blockDim, ...), each
+  // thread keeps their weights in registers for pass 3.
+  constexpr int KC = Bins::kStaged ? 8 : 1;
+  const bool cached = Bins::kStaged && blockDim.x == kThermoThreads && bins <= KC * kThermoThreads;
+  double wc[KC][P];
   double acc[3 * P];
 #pragma unroll
   for (int j = 0; j < 3 * P; ++j) acc[j] = 0.0;
   if (m[0] != -INFINITY) {   // all points see the same nonzero bins
-    for (int i = threadIdx.x; i < bins; i += blockDim.x) {
-      double lg, E, M;
-      if (!B.get(i, lg, E, M)) continue;
+    if (cached) {
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        if (j >= cnt) break;
-        const double w = exp(lg - (E - hv[j] * M) * inv_T - m[j]);
-        acc[3 * j] += w;
-        acc[3 * j + 1] += w * E;
-        acc[3 * j + 2] += w * M;
+      for (int k = 0; k < KC; ++k) {
+        const int i = int(threadIdx.x) + k * kThermoThreads;
+        double lg, E, M;
+        if (i >= bins || !B.get(i, lg, E, M)) continue;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (j >= cnt) break;
+          const double w = exp(lg - (E - hv[j] * M) * inv_T - m[j]);
+          wc[k][j] = w;
+          acc[3 * j] += w;
+          acc[3 * j + 1] += w * E;
+          acc[3 * j + 2] += w * M;
+        }
+      }
+    } else {
+      for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+        double lg, E, M;
+        if (!B.get(i, lg, E, M)) continue;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (j >= cnt) break;
+          const double w = exp(lg - (E - hv[j] * M) * inv_T - m[j]);
+          acc[3 * j] += w;
+          acc[3 * j + 1] += w * E;
+          acc[3 * j + 2] += w * M;
+        }
       }
     }
   }
@@ -236,17 +261,35 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
   if (want_second && m[0] != -INFINITY) {
 #pragma unroll
     for (int j = 0; j < 3 * P; ++j) acc[j] = 0.0;
-    for (int i = threadIdx.x; i < bins; i += blockDim.x) {
-      double lg, E, M;
-      if (!B.get(i, lg, E, M)) continue;
+    if (cached) {
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        if (j >= cnt) break;
-        const double w = exp(lg - (E - hv[j] * M) * inv_T - m[j]);
-        const double dH = (E - hv[j] * M) - (mE[j] - hv[j] * mM[j]), dM = M - mM[j];
-        acc[3 * j] += w * dH * dH;
-        acc[3 * j + 1] += w * dM * dM;
-        acc[3 * j + 2] += w * dH * dM;
+      for (int k = 0; k < KC; ++k) {
+        const int i = int(threadIdx.x) + k * kThermoThreads;
+        double lg, E, M;
+        if (i >= bins || !B.get(i, lg, E, M)) continue;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (j >= cnt) break;
+          const double w = wc[k][j];
+          const double dH = (E - hv[j] * M) - (mE[j] - hv[j] * mM[j]), dM = M - mM[j];
+          acc[3 * j] += w * dH * dH;
+          acc[3 * j + 1] += w * dM * dM;
+          acc[3 * j + 2] += w * dH * dM;
+        }
+      }
+    } else {
+      for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+        double lg, E, M;
+        if (!B.get(i, lg, E, M)) continue;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (j >= cnt) break;
+          const double w = exp(lg - (E - hv[j] * M) * inv_T - m[j]);
+          const double dH = (E - hv[j] * M) - (mE[j] - hv[j] * mM[j]), dM = M - mM[j];
+          acc[3 * j] += w * dH * dH;
+          acc[3 * j + 1] += w * dM * dM;
+          acc[3 * j + 2] += w * dH * dM;
+        }
       }
     }
     block_sums(acc, sh);
