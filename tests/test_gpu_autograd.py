@@ -169,6 +169,38 @@ def test_torus8x5_pm_backward_sampled_bonds_match_transfer_matrix(api, symmetric
 
 
 @pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
+@pytest.mark.parametrize("dims,seed,every", [((4, 8), 41, 1), ((8, 4), 42, 1), ((5, 6), 43, 7)])
+def test_four_valued_tori_with_hi_bits_match_transfer_matrix(api, dims, seed, every, symmetric):
+    # Tori of 30-32 spins with couplings in {-2, -1, 1, 2} (four coupling
+    # classes): beyond 28 spins the walk has hi bits, so pairs with hi bits
+    # take the summation by parts; every bond (every 7th on 5x6) against the
+    # oracle's transfer-matrix split.
+    lx, ly = dims
+    lat = L.square_torus(lx, ly, L.choice_couplings(2 * lx * ly, seed, (-2, -1, 1, 2)))
+    Jh, Jv = L.torus_coupling_grids(lat)
+    g = native.tm_torus(Jh, Jv)
+    rng = np.random.default_rng(seed)
+    W = np.where(g > 0, rng.standard_normal(g.shape) * np.exp(-rng.uniform(0, 3, g.shape)), 0.0)
+    plan = api.Plan(lat)
+    kinds = _bond_kinds(plan, lat)
+    print(f"{lx}x{ly}: N={lat.n_spins} bond kinds", {k: len(v) for k, v in sorted(kinds.items())}, flush=True)
+    assert any(k.endswith("-hi") for k in kinds)
+    dJ = api.bond_backward(plan, torch.from_numpy(W).cuda(), symmetric=symmetric).cpu().numpy()
+    scale = (np.abs(W) * g.astype(np.float64)).sum()
+    for b in range(0, lat.n_bonds, every):
+        key = (dims, seed, b)
+        if key not in _TM_SPLITS:
+            g2, gp = native.tm_torus_bond_split(Jh, Jv, *_torus_bond(lat, b))
+            assert np.array_equal(g2, g)
+            _TM_SPLITS[key] = gp
+        ref = grad.bond_grad_from_weights(g, _TM_SPLITS[key][None], W)[0]
+        assert abs(dJ[b] - ref) <= 1e-13 * scale, (b, dJ[b], ref, scale)
+
+
+_TM_SPLITS = {}   # transfer-matrix bond splits, shared by the full and halved cases
+
+
+@pytest.mark.parametrize("symmetric", [False, True], ids=["full", "halved"])
 def test_torus6x6_backward_random_weights_equal_on_every_bond(api, symmetric):
     # On the edge-transitive 6x6 torus at uniform J every bond has the same
     # split table, so for any W(E, M) all 72 bond sums agree; one horizontal and
