@@ -68,33 +68,12 @@ __device__ __forceinline__ void block_sums(double (&v)[N], double *sh) {
   __syncthreads();
 }
 
-template <int N>
-__device__ __forceinline__ void block_maxes(double (&v)[N], double *sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int j = 0; j < N; ++j) v[j] = wave_max(v[j]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) sh[wv * N + j] = v[j];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    double t = -INFINITY;
-    for (int w = 0; w < nw; ++w) t = fmax(t, sh[w * N + j]);
-    v[j] = t;
-  }
-  __syncthreads();
-}
-
 // Output arrays of the FP64 evaluation; any may be NULL.
 struct ThermoOut {
   double *logz, *mean_E, *mean_M, *heat, *susc;   // value and moments
   double *d_T, *d_h, *d_TT, *d_Th, *d_hh;         // derivatives of log Z
 };
 
-constexpr int kHPerBlock = 4;   // field values one block evaluates at one temperature
 constexpr int kStageBins = 4096;  // nonzero bins a block keeps in LDS as (ln g, E, M)
 
 // Bins of a dense table, read in place: zero bins are skipped, ln g computed.
@@ -172,13 +151,21 @@ __device__ int stage_bins(const unsigned long long *__restrict__ g, int n_e, int
   return total;
 }
 
-// All outputs at temperature T and the fields h[0 .. cnt) (cnt <= kHPerBlock)
-// of one table, written at indices pt0 + j.  Each bin is read once per pass
-// for all cnt points.
+// All outputs at temperature T and the fields h[0 .. cnt) (cnt <= kWaveFields)
+// of one table, written at indices pt0 + j, by one wave: its lanes take the
+// bins lane, lane + 64, ... and every sum or maximum over them is a fixed
+// shuffle tree (the same value in every lane, independent of timing).  Each
+// pass reads every bin once for all cnt points.  When the bins are staged
+// and a lane holds at most kCacheBins of them, the lane keeps the weights of
+// the second pass in registers for the third.
+constexpr int kWaveFields = 2;
+constexpr int kCacheBins = 32;
+
 template <class Bins>
-__device__ void thermo_points(const Bins &B, double T, const double *__restrict__ h, int cnt, int pt0,
-                              const ThermoOut &o, double *sh) {
-  constexpr int P = kHPerBlock;
+__device__ void wave_points(const Bins &B, double T, const double *__restrict__ h, int cnt, int pt0,
+                            const ThermoOut &o) {
+  constexpr int P = kWaveFields;
+  const int lane = threadIdx.x & 63;
   const int bins = B.count();
   const bool want_second = o.heat || o.susc || o.d_TT || o.d_Th || o.d_hh;
   double *const all[10] = {o.logz, o.mean_E, o.mean_M, o.heat, o.susc, o.d_T, o.d_h, o.d_TT, o.d_Th, o.d_hh};
@@ -196,22 +183,21 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
   double m[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) m[j] = -INFINITY;
-  for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+  for (int i = lane; i < bins; i += 64) {
     double lg, E, M;
     if (!B.get(i, lg, E, M)) continue;
 #pragma unroll
     for (int j = 0; j < P; ++j)
       if (j < cnt) m[j] = fmax(m[j], lg - (E - hv[j] * M) * inv_T);
   }
-  block_maxes(m, sh);
+#pragma unroll
+  for (int j = 0; j < P; ++j) m[j] = wave_max(m[j]);
 #pragma unroll
   for (int j = cnt; j < P; ++j) m[j] = m[0];
 
-  // pass 2: Z' and first moments.  When the bins are staged and a full
-  // block holds at most KC per thread (bins i = t, t + blockDim, ...), each
-  // thread keeps their weights in registers for pass 3.
-  constexpr int KC = Bins::kStaged ? 8 : 1;
-  const bool cached = Bins::kStaged && blockDim.x == kThermoThreads && bins <= KC * kThermoThreads;
+  // pass 2: Z' and first moments
+  constexpr int KC = Bins::kStaged ? kCacheBins : 1;
+  const bool cached = Bins::kStaged && bins <= KC * 64;
   double wc[KC][P];
   double acc[3 * P];
 #pragma unroll
@@ -220,7 +206,7 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
     if (cached) {
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
-        const int i = int(threadIdx.x) + k * kThermoThreads;
+        const int i = lane + 64 * k;
         double lg, E, M;
         if (i >= bins || !B.get(i, lg, E, M)) continue;
 #pragma unroll
@@ -234,7 +220,7 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
         }
       }
     } else {
-      for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+      for (int i = lane; i < bins; i += 64) {
         double lg, E, M;
         if (!B.get(i, lg, E, M)) continue;
 #pragma unroll
@@ -248,7 +234,8 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
       }
     }
   }
-  block_sums(acc, sh);
+#pragma unroll
+  for (int j = 0; j < 3 * P; ++j) acc[j] = wave_sum(acc[j]);
   double mE[P], mM[P], z[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -264,7 +251,7 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
     if (cached) {
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
-        const int i = int(threadIdx.x) + k * kThermoThreads;
+        const int i = lane + 64 * k;
         double lg, E, M;
         if (i >= bins || !B.get(i, lg, E, M)) continue;
 #pragma unroll
@@ -278,7 +265,7 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
         }
       }
     } else {
-      for (int i = threadIdx.x; i < bins; i += blockDim.x) {
+      for (int i = lane; i < bins; i += 64) {
         double lg, E, M;
         if (!B.get(i, lg, E, M)) continue;
 #pragma unroll
@@ -292,10 +279,11 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
         }
       }
     }
-    block_sums(acc, sh);
+#pragma unroll
+    for (int j = 0; j < 3 * P; ++j) acc[j] = wave_sum(acc[j]);
   }
 
-  if (threadIdx.x != 0) return;
+  if (lane != 0) return;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     if (j >= cnt) break;
@@ -331,44 +319,32 @@ __device__ void thermo_points(const Bins &B, double T, const double *__restrict_
 }
 
 // A block's table: its nonzero bins are staged in LDS once (ln g taken once
-// per bin), then every lane of every pass works on a real bin; tables with
-// more nonzero bins than fit are read in place.
-constexpr int kTPerBlock = 8;   // temperatures per block of the batched kernel
-
+// per bin) for the block's waves, so every lane of every pass works on a real
+// bin; tables with more nonzero bins than fit are read in place.
 struct StageLds {
   double lg[kStageBins];
   int E[kStageBins], M[kStageBins];
   int scan[kThermoThreads / 64 + 1];
-  double sh[(kThermoThreads / 64) * 3 * kHPerBlock];
 };
 
-// Temperatures [a0, a1) x field groups [c_lo, c_hi) (in units of
-// kHPerBlock) of one table.
-__device__ void thermo_block(const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
-                             const double *__restrict__ Tg, int a0, int a1, const double *__restrict__ hg, int nh,
-                             int c_lo, int c_hi, int out_base, const ThermoOut &o, StageLds &L) {
-  const int staged = stage_bins(g, n_e, n_m, e_min, n_spins, L.lg, L.E, L.M, L.scan);
-  for (int a = a0; a < a1; ++a)
-    for (int cg = c_lo; cg < c_hi; ++cg) {
-      const int c0 = cg * kHPerBlock;
-      const int cnt = min(kHPerBlock, nh - c0), pt0 = out_base + a * nh + c0;
-      if (staged >= 0)
-        thermo_points(StagedBins{L.lg, L.E, L.M, staged}, Tg[a], hg + c0, cnt, pt0, o, L.sh);
-      else
-        thermo_points(DenseBins{g, n_m, e_min, n_spins, n_e * n_m}, Tg[a], hg + c0, cnt, pt0, o, L.sh);
-    }
-}
+constexpr int kWavesPerBlock = kThermoThreads / 64;
 
-// One table: grid (ceil(nT / kTSingle), ceil(nh / kHPerBlock)); block (x, y)
-// covers kTSingle temperatures and one field group; outputs [nT][nh].
-constexpr int kTSingle = 2;
-
+// One table: wave u of the grid (4 per block) takes temperature u / n_fg and
+// the field group u % n_fg (kWaveFields fields each); outputs [nT][nh].
 __global__ __launch_bounds__(kThermoThreads) void k_thermo(
     const unsigned long long *__restrict__ g, int n_e, int n_m, int e_min, int n_spins,
     const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh, ThermoOut o) {
   __shared__ StageLds L;
-  const int a0 = blockIdx.x * kTSingle, a1 = min(nT, a0 + kTSingle);
-  thermo_block(g, n_e, n_m, e_min, n_spins, Tg, a0, a1, hg, nh, blockIdx.y, blockIdx.y + 1, 0, o, L);
+  const int staged = stage_bins(g, n_e, n_m, e_min, n_spins, L.lg, L.E, L.M, L.scan);
+  const int n_fg = (nh + kWaveFields - 1) / kWaveFields;
+  const int64_t u = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / 64;
+  if (u >= int64_t(nT) * n_fg) return;
+  const int a = int(u / n_fg), c0 = int(u % n_fg) * kWaveFields;
+  const int cnt = min(kWaveFields, nh - c0), pt0 = a * nh + c0;
+  if (staged >= 0)
+    wave_points(StagedBins{L.lg, L.E, L.M, staged}, Tg[a], hg + c0, cnt, pt0, o);
+  else
+    wave_points(DenseBins{g, n_m, e_min, n_spins, n_e * n_m}, Tg[a], hg + c0, cnt, pt0, o);
 }
 
 // One thread block per dense bin; its threads split the (T, h) points and the
@@ -576,8 +552,9 @@ ising_status first_derivatives_launch(const uint64_t *g, int32_t n_e, int32_t n_
   return ISING_OK;
 }
 
-// Batched: grid (ceil(nT / kTPerBlock), members); block (x, member) covers
-// kTPerBlock temperatures and every field; outputs [member][nT][nh].
+// Batched: grid (ceil(nT / 4), members); wave w of block (x, member) takes
+// temperature 4 x + w and every field group in turn; outputs
+// [member][nT][nh].
 __global__ __launch_bounds__(kThermoThreads) void k_batch_thermo(
     const unsigned long long *__restrict__ g_all, const BatchMember *__restrict__ meta,
     const double *__restrict__ Tg, int nT, const double *__restrict__ hg, int nh,
@@ -587,9 +564,17 @@ __global__ __launch_bounds__(kThermoThreads) void k_batch_thermo(
   const int member = blockIdx.y;
   const BatchMember mb = meta[member];
   const ThermoOut o{logz, mean_E, mean_M, heat, susc, nullptr, nullptr, nullptr, nullptr, nullptr};
-  const int a0 = blockIdx.x * kTPerBlock, a1 = min(nT, a0 + kTPerBlock);
-  thermo_block(g_all + mb.offset, mb.n_e, mb.n_m, mb.e_min, mb.n_spins, Tg, a0, a1, hg, nh, 0,
-               (nh + kHPerBlock - 1) / kHPerBlock, member * nT * nh, o, L);
+  const unsigned long long *g = g_all + mb.offset;
+  const int staged = stage_bins(g, mb.n_e, mb.n_m, mb.e_min, mb.n_spins, L.lg, L.E, L.M, L.scan);
+  const int a = int(blockIdx.x) * kWavesPerBlock + int(threadIdx.x / 64);
+  if (a >= nT) return;
+  for (int c0 = 0; c0 < nh; c0 += kWaveFields) {
+    const int cnt = min(kWaveFields, nh - c0), pt0 = (member * nT + a) * nh + c0;
+    if (staged >= 0)
+      wave_points(StagedBins{L.lg, L.E, L.M, staged}, Tg[a], hg + c0, cnt, pt0, o);
+    else
+      wave_points(DenseBins{g, mb.n_m, mb.e_min, mb.n_spins, mb.n_e * mb.n_m}, Tg[a], hg + c0, cnt, pt0, o);
+  }
 }
 
 ising_status batch_thermo_launch(const BatchMember *meta_dev, int n_members, const uint64_t *g_all,
@@ -598,7 +583,7 @@ ising_status batch_thermo_launch(const BatchMember *meta_dev, int n_members, con
   if (nT == 0 || nh == 0 || n_members == 0) return ISING_OK;
   if (!T_dev || !h_dev) return fail(ISING_EINVAL, "T_dev or h_dev is NULL");
   if (int64_t(nT) * nh > (int64_t(1) << 30) || n_members > 65535) return fail(ISING_EINVAL, "grid too large");
-  hipLaunchKernelGGL(k_batch_thermo, dim3(unsigned((nT + kTPerBlock - 1) / kTPerBlock), unsigned(n_members)),
+  hipLaunchKernelGGL(k_batch_thermo, dim3(unsigned((nT + kWavesPerBlock - 1) / kWavesPerBlock), unsigned(n_members)),
                      dim3(kThermoThreads), 0,
                      stream, reinterpret_cast<const unsigned long long *>(g_all), meta_dev, T_dev, nT, h_dev, nh,
                      logz, mE, mM, C, chi);
@@ -660,8 +645,8 @@ static ising_status thermo_launch(const uint64_t *g_dev, int32_t n_e, int32_t n_
   if (st != ISING_OK) return st;
   if (nT == 0 || nh == 0) return ISING_OK;
   if (!T_dev || !h_dev) return fail(ISING_EINVAL, "T_dev or h_dev is NULL");
-  const dim3 grid(unsigned((nT + kTSingle - 1) / kTSingle), unsigned((nh + kHPerBlock - 1) / kHPerBlock));
-  if (grid.y > 65535) return fail(ISING_EINVAL, "too many field values");
+  const int64_t waves = int64_t(nT) * ((nh + kWaveFields - 1) / kWaveFields);
+  const dim3 grid(unsigned((waves + kWavesPerBlock - 1) / kWavesPerBlock));
   hipLaunchKernelGGL(k_thermo, grid, dim3(kThermoThreads), 0, static_cast<hipStream_t>(stream),
                      reinterpret_cast<const unsigned long long *>(g_dev), n_e, n_m, e_min, n_spins, T_dev, nT,
                      h_dev, nh, o);
