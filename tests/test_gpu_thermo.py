@@ -51,6 +51,38 @@ def test_logz_and_moments_match_oracle(api, name):
     np.testing.assert_allclose(out["susceptibility"].cpu().numpy(), chi, rtol=RTOL, atol=1e-300)
 
 
+@pytest.mark.parametrize("nT,nh", [(1, 1), (7, 5), (3, 9), (13, 2)])
+def test_ragged_grids(api, nT, nh):
+    # grids whose temperature count is not a multiple of a block's waves and
+    # whose field count is odd (a wave's second field slot unused), on the
+    # +-J 8x5 table; the batched form on the same grid with two small members
+    lat = L.workload("torus8x5_pm")["lattice"]
+    g_ref = _ref_g(lat)
+    g = torch.from_numpy(g_ref.view(np.int64)).view(torch.uint64).cuda()
+    S, N = lat.abs_coupling_sum, lat.n_spins
+    rng = np.random.default_rng(nT * 100 + nh)
+    T = np.sort(rng.uniform(0.3, 6.0, nT))
+    h = rng.uniform(-2.0, 2.0, nh)
+    out = api.moments(g, -S, N, T, h)
+    ref_lz = thermo.log_z(g_ref, -S, N, T, h)
+    mE, mM, C, chi = thermo.moments(g_ref, -S, N, T, h)
+    np.testing.assert_allclose(out["log_z"].cpu().numpy(), ref_lz, rtol=RTOL, atol=0)
+    np.testing.assert_allclose(out["mean_E"].cpu().numpy(), mE, rtol=RTOL, atol=RTOL * S)
+    np.testing.assert_allclose(out["mean_M"].cpu().numpy(), mM, rtol=RTOL, atol=RTOL * N)
+    np.testing.assert_allclose(out["heat_capacity"].cpu().numpy(), C, rtol=RTOL, atol=1e-300)
+    np.testing.assert_allclose(out["susceptibility"].cpu().numpy(), chi, rtol=RTOL, atol=1e-300)
+    members = [L.square_torus(3, 4, L.pm_couplings(24, 5)), L.square_torus(4, 5, L.pm_couplings(40, 6))]
+    batch = api.BatchPlan(members)
+    tables = api.batch_enumerate(batch)
+    bm = api.batch_moments(batch, tables, T, h)
+    for k, lt in enumerate(members):
+        gr = native.count_all(lt.n_spins, lt.bond_i, lt.bond_j, lt.bond_J)
+        ref = thermo.log_z(gr, -lt.abs_coupling_sum, lt.n_spins, T, h)
+        np.testing.assert_allclose(bm["log_z"][k].cpu().numpy(), ref, rtol=RTOL, atol=0)
+        refC = thermo.moments(gr, -lt.abs_coupling_sum, lt.n_spins, T, h)[2]
+        np.testing.assert_allclose(bm["heat_capacity"][k].cpu().numpy(), refC, rtol=RTOL, atol=1e-300)
+
+
 def test_table_with_more_bins_than_the_lds_stage(api):
     # A 22-spin triangular patch with 8 widely spaced couplings has ~8300
     # nonzero bins, more than the 4096 the thermo kernels stage in LDS, so they
